@@ -1,0 +1,235 @@
+"""Seeded synthetic inputs for the wave-equation operators.
+
+This module only draws and shapes INPUTS: velocity / anisotropy models,
+source and receiver coordinates, and source wavelets.  It contains none of the
+operators' arithmetic (no stencils, no interpolation weights, no damping), so
+that the CPU oracle and the HIP path can both consume the same inputs.
+
+Every floating-point model value and wavelet sample is rounded to float32 and
+returned as float64, so both sides see bit-identical parameters; coordinates
+stay float64 (both sides derive their interpolation data from them in FP64).
+
+Arrays use the logical layout with the first axis fastest: numpy shape
+(nz, ny, nx) for a 3D grid whose axes are (x, y, z), (nz, nx) for 2D (x, z).
+
+Workload recipes follow the paper's test-case setup (arXiv 1807.03032,
+Section 7.2: cubic grids, space orders 4-16, zero initial conditions,
+damping layer, one seismic source wavelet, CFL-chosen time step).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional
+
+import numpy as np
+
+SPACE_ORDERS = (2, 4, 6, 8, 10, 12, 14, 16)
+
+
+def f32(a):
+    """Round to float32 and hand back float64 (identical values on both sides)."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def ricker(f0: float, t0: float, dt: float, nt: int, amp: float = 1.0) -> np.ndarray:
+    """Ricker wavelet (1 - 2 pi^2 f0^2 tau^2) exp(-pi^2 f0^2 tau^2), tau = n dt - t0.
+
+    The paper only says 'a time-dependent seismic source wavelet' (Section 7.2);
+    the Ricker wavelet is the customary choice.
+    """
+    tau = np.arange(nt, dtype=np.float64) * dt - t0
+    a = (math.pi * f0 * tau) ** 2
+    return f32(amp * (1.0 - 2.0 * a) * np.exp(-a))
+
+
+def cfl_dt(h_min: float, v_eff: float, ndim: int, factor: float = 0.4) -> float:
+    """dt = factor * h_min / (v_eff sqrt(ndim)) (the configs' 'dt = 0.4 CFL')."""
+    return factor * h_min / (v_eff * math.sqrt(ndim))
+
+
+def smooth_field(shape_xyz, seed: int, lo: float, hi: float, sigma_pts: float = 10.0) -> np.ndarray:
+    """Smooth seeded random field rescaled to [lo, hi].
+
+    Recipe: white noise N(0,1) drawn with numpy PCG64(seed) on a coarse grid
+    (one node every `step` points, step = max(1, round(sigma_pts/2))), a
+    separable Gaussian filter of sigma = sigma_pts/step coarse nodes (truncated
+    at 3 sigma, reflecting edges), min-max rescale to [lo, hi], then
+    multilinear interpolation onto the full grid (values stay in [lo, hi]).
+    """
+    from scipy import ndimage
+
+    shape = tuple(reversed([int(s) for s in shape_xyz]))  # numpy order
+    step = max(1, int(round(sigma_pts / 2.0)))
+    coarse = tuple(max(2, (s - 1 + step - 1) // step + 1) for s in shape)
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(coarse)
+    w = ndimage.gaussian_filter(w, sigma=sigma_pts / step, truncate=3.0, mode="reflect")
+    wmin, wmax = float(w.min()), float(w.max())
+    w = (w - wmin) / (wmax - wmin) if wmax > wmin else np.zeros_like(w)
+    w = lo + (hi - lo) * w
+    # multilinear upsampling, one axis at a time
+    out = w
+    for ax, n in enumerate(shape):
+        pos = np.arange(n, dtype=np.float64) / step
+        pos = np.minimum(pos, out.shape[ax] - 1)
+        i0 = np.minimum(np.floor(pos).astype(np.int64), out.shape[ax] - 2)
+        fr = pos - i0
+        a0 = np.take(out, i0, axis=ax)
+        a1 = np.take(out, i0 + 1, axis=ax)
+        bshape = [1] * out.ndim
+        bshape[ax] = n
+        fr = fr.reshape(bshape)
+        out = a0 * (1.0 - fr) + a1 * fr
+    return np.clip(out, lo, hi)
+
+
+@dataclasses.dataclass
+class Problem:
+    """One forward-modelling shot: grid, model, sources, receivers, time axis."""
+
+    name: str
+    kind: str                      # "iso" or "tti"
+    shape: tuple                   # (nx, nz) or (nx, ny, nz)
+    extent: tuple
+    origin: tuple
+    so: int
+    nbl: int
+    nt: int
+    dt: float
+    vmax: float
+    eps_max: float
+    fields: Dict[str, np.ndarray]  # m (and eps, delta, theta, phi for tti), numpy order
+    src_coords: np.ndarray         # [nsrc][ndim]
+    src: np.ndarray                # [nt][nsrc]
+    rec_coords: np.ndarray         # [nrec][ndim]
+    rc: float = 1e-3               # damping reflection coefficient
+
+    @property
+    def ndim(self):
+        return len(self.shape)
+
+    @property
+    def spacing(self):
+        return tuple(e / (n - 1) for e, n in zip(self.extent, self.shape))
+
+    @property
+    def npoints(self):
+        return int(np.prod(self.shape))
+
+    @property
+    def array_shape(self):
+        return tuple(reversed(self.shape))
+
+
+def _physical_models(kind, shape, v, seed0, eps_range=(0.0, 0.3), delta_range=(0.0, 0.2),
+                     angle_range=(0.0, math.pi / 4), sigma_pts=10.0):
+    """m = 1/v^2 plus, for TTI, eps, delta (clamped to delta <= eps), theta, phi."""
+    fields = {"m": f32(1.0 / (v * v))}
+    eps_max = 0.0
+    if kind == "tti":
+        eps = f32(smooth_field(shape, seed0 + 1, *eps_range, sigma_pts=sigma_pts))
+        delta = smooth_field(shape, seed0 + 2, *delta_range, sigma_pts=sigma_pts)
+        # model-generation rule: delta <= eps keeps the coupled system well posed
+        delta = f32(np.minimum(delta, eps))
+        theta = f32(smooth_field(shape, seed0 + 3, *angle_range, sigma_pts=sigma_pts))
+        fields.update(eps=eps, delta=delta, theta=theta)
+        if len(shape) == 3:
+            fields["phi"] = f32(smooth_field(shape, seed0 + 4, *angle_range, sigma_pts=sigma_pts))
+        eps_max = float(eps.max())
+    return fields, eps_max
+
+
+def _receiver_plane(n_x, n_y, h, x_extent, y_extent, z0, seeds):
+    """n_x*n_y receivers at jittered lattice positions, x fastest in the ordering."""
+    gx = np.random.default_rng(seeds[0]).uniform(-0.5, 0.5, size=(n_y, n_x))
+    gy = np.random.default_rng(seeds[1]).uniform(-0.5, 0.5, size=(n_y, n_x))
+    gz = np.random.default_rng(seeds[2]).uniform(0.0, 1.0, size=(n_y, n_x))
+    ix = np.arange(n_x)[None, :]
+    iy = np.arange(n_y)[:, None]
+    x = np.clip((ix + gx) * h, 0.0, x_extent)
+    y = np.clip((iy + gy) * h, 0.0, y_extent)
+    z = z0 + gz * h
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+
+
+def config_2d_iso_101(nt: Optional[int] = None) -> Problem:
+    """2D isotropic, 101x101, h = 10 m, v = 1500 m/s, so = 4, 500 steps, nbl = 20,
+    10 Hz Ricker at the centre node, 101 receivers on a row 20 m below the layer."""
+    shape, h, v, nbl = (101, 101), 10.0, 1500.0, 20
+    nt = 500 if nt is None else nt
+    extent = tuple(h * (n - 1) for n in shape)
+    dt = cfl_dt(h, v, 2)
+    vel = np.full(tuple(reversed(shape)), v)
+    fields, _ = _physical_models("iso", shape, vel, 0)
+    src_coords = np.array([[500.0, 500.0]])
+    src = ricker(10.0, 0.1, dt, nt)[:, None]
+    rec_coords = np.stack([np.arange(101) * 10.0, np.full(101, (nbl + 2) * h)], axis=1)
+    return Problem("2d_iso_101x101_so4", "iso", shape, extent, (0.0, 0.0), 4, nbl, nt, dt, v, 0.0,
+                   fields, src_coords, f32(src), rec_coords)
+
+
+def config_3d_iso_256(nt: Optional[int] = None, n: int = 256) -> Problem:
+    """3D isotropic, 256^3, h = 10 m, v = 1500 / 2500 m/s split at mid-depth,
+    so = 8, nbl = 40, 1000 steps, 15 Hz Ricker near the surface,
+    256x256 jittered receiver plane (trilinear interpolation)."""
+    shape, h, nbl = (n, n, n), 10.0, 40
+    nt = 1000 if nt is None else nt
+    extent = tuple(h * (k - 1) for k in shape)
+    vel = np.full(tuple(reversed(shape)), 1500.0)
+    vel[n // 2:, :, :] = 2500.0  # numpy axis 0 is z (depth)
+    dt = cfl_dt(h, 2500.0, 3)
+    fields, _ = _physical_models("iso", shape, vel, 0)
+    src_coords = np.array([[extent[0] / 2, extent[1] / 2, (nbl + 2.5) * h]])
+    src = ricker(15.0, 1.0 / 15.0, dt, nt)[:, None]
+    rec_coords = _receiver_plane(n, n, h, extent[0], extent[1], (nbl + 2) * h, (2, 3, 4))
+    return Problem(f"3d_iso_{n}cube_so8", "iso", shape, extent, (0.0,) * 3, 8, nbl, nt, dt, 2500.0, 0.0,
+                   fields, src_coords, f32(src), rec_coords)
+
+
+def config_3d_tti_512(nt: Optional[int] = None, n: int = 512) -> Problem:
+    """3D TTI, 512^3, h = 12.5 m, so = 12, nbl = 40, 800 steps; smooth seeded random
+    v in [1500, 4500], eps in [0, 0.3], delta in [0, 0.2] (<= eps), theta, phi in
+    [0, pi/4]; 10 Hz Ricker at the centre near the surface; 512x512 receivers."""
+    shape, h, nbl = (n, n, n), 12.5, 40
+    nt = 800 if nt is None else nt
+    extent = tuple(h * (k - 1) for k in shape)
+    v = smooth_field(shape, 11, 1500.0, 4500.0)
+    fields, eps_max = _physical_models("tti", shape, v, 11)
+    vmax = 4500.0
+    dt = cfl_dt(h, vmax * math.sqrt(1.0 + 2.0 * 0.3), 3)
+    src_coords = np.array([[extent[0] / 2, extent[1] / 2, (nbl + 2.5) * h]])
+    src = ricker(10.0, 0.1, dt, nt)[:, None]
+    rec_coords = _receiver_plane(n, n, h, extent[0], extent[1], (nbl + 2) * h, (16, 17, 18))
+    return Problem(f"3d_tti_{n}cube_so12", "tti", shape, extent, (0.0,) * 3, 12, nbl, nt, dt, vmax, eps_max,
+                   fields, src_coords, f32(src), rec_coords)
+
+
+def small_problem(kind: str, shape, so: int, nt: int, seed: int = 0, nsrc: int = 1, nrec: int = 16,
+                  nbl: int = 4, h: float = 10.0, vrange=(1500.0, 3000.0), src_at=None,
+                  rec_coords=None, f0: Optional[float] = None, sigma_pts: float = 4.0) -> Problem:
+    """A small seeded problem of any shape for parity tests: smooth random models,
+    sources and receivers at random positions anywhere in the grid (edges
+    included), a Ricker wavelet per source with jittered delay."""
+    shape = tuple(int(s) for s in shape)
+    ndim = len(shape)
+    extent = tuple(h * (k - 1) for k in shape)
+    v = smooth_field(shape, seed + 100, vrange[0], vrange[1], sigma_pts=sigma_pts)
+    fields, eps_max = _physical_models(kind, shape, v, seed + 100, sigma_pts=sigma_pts)
+    vmax = float(vrange[1])
+    v_eff = vmax * math.sqrt(1.0 + 2.0 * 0.3) if kind == "tti" else vmax
+    dt = cfl_dt(h, v_eff, ndim)
+    rng = np.random.default_rng(seed + 200)
+    if src_at is not None:
+        src_coords = np.asarray(src_at, dtype=np.float64).reshape(-1, ndim)
+    else:
+        src_coords = rng.uniform(0.0, 1.0, size=(nsrc, ndim)) * np.asarray(extent)
+    ns = src_coords.shape[0]
+    if f0 is None:
+        f0 = vrange[0] / (8.0 * h)  # about 8 points per wavelength at the peak frequency
+    src = np.stack([ricker(f0, (1.0 + 0.2 * k) / f0, dt, nt) for k in range(ns)], axis=1)
+    if rec_coords is None:
+        rec_coords = rng.uniform(0.0, 1.0, size=(nrec, ndim)) * np.asarray(extent)
+    return Problem(f"small_{kind}_{'x'.join(map(str, shape))}_so{so}", kind, shape, extent, (0.0,) * ndim,
+                   so, nbl, nt, dt, vmax, eps_max, fields, src_coords, f32(src).reshape(nt, ns),
+                   np.asarray(rec_coords, dtype=np.float64).reshape(-1, ndim))
