@@ -1,0 +1,208 @@
+/*
+ * fdw.h — C ABI of the MI355X (gfx950) finite-difference wave-equation
+ * operators: isotropic acoustic and TTI pseudo-acoustic time marching with a
+ * damping layer, sparse source injection and receiver interpolation.
+ *
+ * The calls mirror the problem statement of arXiv 1807.03032 (Devito):
+ *   Grid(shape, extent, origin)                 -> fdw_grid_create        (Section 3.1)
+ *   Function / TimeFunction(space_order, ...)   -> fdw_function_bind,
+ *                                                  fdw_timefunction_bind  (Section 3.1, 3.5)
+ *   domain / halo / padding regions             -> fdw_field_layout       (Section 3.6)
+ *   SparseTimeFunction(coordinates), inject,
+ *   interpolate                                 -> fdw_sparse_bind        (Section 3.3)
+ *   Operator(eqs) ... op.apply(time=...)        -> fdw_operator_create,
+ *                                                  fdw_operator_apply     (Section 4 intro, 4.8)
+ *
+ * Conventions shared by every call
+ *  - Status: every int-returning call returns FDW_OK (0) or a negative FDW_ERR_*
+ *    code; fdw_last_error() returns a thread-local message for the last
+ *    failure on the calling thread.  No C++ exception crosses the ABI.  A
+ *    failed call leaves no partially built object and writes nothing to *out.
+ *  - Ownership: device buffers passed in (fields, sparse data, receiver
+ *    traces) are BORROWED: the library never frees them and the caller keeps
+ *    them alive while any handle that references them exists.  Handles
+ *    (fdw_grid, fdw_func, fdw_tfunc, fdw_sparse, fdw_op) are owned by the
+ *    library and released with the matching *_destroy call.  A handle may be
+ *    destroyed only after every handle built from it has been destroyed.
+ *  - Threads: handles are not thread-safe; distinct operators may be used from
+ *    distinct threads and streams.
+ *  - Axes: 2D grids have axes (x, z), 3D grids (x, y, z), z being depth.
+ *    Memory is x-fastest (see fdw_field_layout).
+ *  - Precision: fields are float32; coordinates and scalars are double and
+ *    every derived coefficient is computed in double and rounded once.
+ */
+#ifndef FDW_H
+#define FDW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDW_OK 0
+#define FDW_ERR_ARG (-1)      /* invalid argument (NULL, range, mismatch)           */
+#define FDW_ERR_DOMAIN (-2)   /* a sparse coordinate lies outside the grid          */
+#define FDW_ERR_UNSTABLE (-3) /* dt above the stability bound                       */
+#define FDW_ERR_LAYOUT (-4)   /* buffer too small for the layout, or misaligned     */
+#define FDW_ERR_DEVICE (-5)   /* HIP runtime error (message carries its string)     */
+#define FDW_ERR_NOMEM (-6)    /* host or device allocation failed                   */
+#define FDW_ERR_STATE (-7)    /* call not valid in the object's current state       */
+
+#define FDW_ISO 0 /* isotropic acoustic:  m u_tt - lap u = q                        */
+#define FDW_TTI 1 /* TTI pseudo-acoustic: coupled p, r with rotated operators      */
+
+#define FDW_MAX_SO 16
+#define FDW_X_OFFSET 32 /* floats before logical x = 0 in each row (128-byte alignment) */
+
+typedef struct fdw_grid fdw_grid;
+typedef struct fdw_func fdw_func;
+typedef struct fdw_tfunc fdw_tfunc;
+typedef struct fdw_sparse fdw_sparse;
+typedef struct fdw_op fdw_op;
+
+/* Memory layout of one field (one time slot) for a grid and space order.
+ * Section 3.6 (domain, halo, padding): the halo is R = space_order/2 points
+ * on every side of every axis and must hold zeros (Dirichlet, Section 7.2);
+ * padding aligns logical x = 0 of every row to 128 bytes.
+ *   3D element (x, y, z) at  origin_offset + (z * pitch_y + y) * pitch_x + x
+ *   2D element (x, z)    at  origin_offset +  z * pitch_x + x
+ * A field occupies elems_per_slot floats; a TimeFunction with time_order 2
+ * holds 3 slots back to back, logical time level t in slot t mod 3 (Section
+ * 3.5: u[t % 3]; level -1 lives in slot 2). */
+typedef struct {
+    int ndim;              /* 2 or 3                                              */
+    int halo;              /* R = space_order / 2                                 */
+    int64_t shape[3];      /* points per axis (x, y, z) or (x, z)                 */
+    int64_t pitch_x;       /* floats per row, a multiple of 32                     */
+    int64_t pitch_y;       /* rows per plane: ny + 2R in 3D; nz + 2R in 2D         */
+    int64_t planes;        /* nz + 2R in 3D; 1 in 2D                              */
+    int64_t origin_offset; /* element offset of logical (0, 0[, 0])               */
+    int64_t elems_per_slot;/* pitch_x * pitch_y * planes                          */
+    int alignment_bytes;   /* required alignment of every bound pointer (256)     */
+} fdw_layout;
+
+/* Operator description (Section 4: Operator built once from its equations,
+ * then applied to any data; Section 7.2: the isotropic and TTI test cases).
+ * The library copies the struct; the handles it names must outlive the op. */
+typedef struct {
+    int kind;            /* FDW_ISO or FDW_TTI                                       */
+    int space_order;     /* even, 2..16 (the paper measures 4, 8, 12, 16)             */
+    double dt;           /* time step; must not exceed fdw_stable_dt(...)             */
+    int nbl;             /* damping-layer width in points (0: no damping)             */
+    double damp_rc;      /* layer reflection coefficient, (0,1); 0 selects 1e-3       */
+    double vmax;         /* largest velocity: damping strength and stability check    */
+    double eps_max;      /* TTI: largest epsilon (stability check); ignored for ISO   */
+    fdw_tfunc *u;        /* ISO: wavefield u;   TTI: wavefield p                      */
+    fdw_tfunc *r;        /* TTI: wavefield r;   ISO: NULL                             */
+    fdw_func *m;         /* squared slowness m = 1/v^2 (required)                     */
+    fdw_func *eps;       /* TTI: Thomsen epsilon                                      */
+    fdw_func *delta;     /* TTI: Thomsen delta                                        */
+    fdw_func *theta;     /* TTI: tilt angle (radians)                                 */
+    fdw_func *phi;       /* TTI 3D: azimuth angle (radians); NULL in 2D               */
+    fdw_sparse *src;     /* sources, injected into u (p and r); may be NULL           */
+    fdw_sparse *rec;     /* receivers, sampling u (p); may be NULL                    */
+} fdw_op_desc;
+
+/* Grid(shape, extent, origin), Section 3.1.  ndim in {2, 3}; shape[a] >= 2;
+ * extent[a] > 0; spacing h_a = extent[a] / (shape[a] - 1).  origin may be
+ * NULL (all zeros).  The shape is the computational domain, absorbing layer
+ * included (Section 3.6).  Errors: FDW_ERR_ARG. */
+int fdw_grid_create(int ndim, const int64_t *shape, const double *extent, const double *origin,
+                    fdw_grid **out);
+int fdw_grid_destroy(fdw_grid *grid);
+
+/* Layout of a field of this grid at this space order (Section 3.6); pure host
+ * arithmetic, no device call.  Errors: FDW_ERR_ARG. */
+int fdw_field_layout(const fdw_grid *grid, int space_order, fdw_layout *out);
+
+/* Function (Section 3.1): a time-invariant parameter field (m, eps, delta,
+ * theta, phi).  dptr: device float buffer of nelem floats in the layout of
+ * (grid, space_order), 256-byte aligned; only domain points are read.
+ * name: informational, copied (may be NULL).
+ * Errors: FDW_ERR_ARG (NULL, bad order), FDW_ERR_LAYOUT (nelem < elems_per_slot
+ * or misaligned). */
+int fdw_function_bind(fdw_grid *grid, const char *name, float *dptr, int64_t nelem, int space_order,
+                      fdw_func **out);
+int fdw_function_destroy(fdw_func *f);
+
+/* TimeFunction (Section 3.1, 3.5): a wavefield with time_order + 1 slots
+ * (time_order must be 2: 3 slots), level t in slot t mod 3.  dptr holds
+ * nelem >= 3 * elems_per_slot floats, 256-byte aligned.  The caller writes the
+ * initial levels -1 and 0 (zeros give the zero initial conditions of eq. WE).
+ * fdw_operator_create zeroes the halo of every slot; the library never writes
+ * it afterwards.  Errors: FDW_ERR_ARG, FDW_ERR_LAYOUT. */
+int fdw_timefunction_bind(fdw_grid *grid, const char *name, float *dptr, int64_t nelem,
+                          int space_order, int time_order, fdw_tfunc **out);
+int fdw_timefunction_destroy(fdw_tfunc *f);
+
+/* SparseTimeFunction (Section 3.3, eq. interp, Listing finject).
+ * coords_host: host array [npoint][ndim] of physical coordinates (copied);
+ * ddata: device float array [nt][npoint] (time-major), source samples read by
+ * injection or receiver samples written by interpolation; may be NULL when
+ * npoint == 0.  Each point must lie in [o_a, o_a + (shape_a - 1) h_a] on
+ * every axis.  Interpolation base b = floor((c - o)/h), clamped to shape - 2;
+ * fraction f = (c - o)/h - b; (bi/tri)linear weights, all in double.
+ * Allocates library-owned device buffers for the derived indices/weights.
+ * Errors: FDW_ERR_ARG, FDW_ERR_DOMAIN, FDW_ERR_NOMEM, FDW_ERR_DEVICE. */
+int fdw_sparse_bind(fdw_grid *grid, const char *name, int npoint, int nt, const double *coords_host,
+                    float *ddata, fdw_sparse **out);
+int fdw_sparse_destroy(fdw_sparse *s);
+
+/* Operator construction (Section 4: built once, applied many times).
+ * Validates kinds, orders, that every field is bound on the same grid at the
+ * operator's space order, dt against fdw_stable_dt, and the sparse data
+ * lengths; builds the per-axis damping tables and FD coefficients (double,
+ * rounded once); allocates the TTI stage buffers; zeroes the halos of the
+ * wavefield slots (on the null stream, synchronously).
+ * Errors: FDW_ERR_ARG, FDW_ERR_UNSTABLE, FDW_ERR_LAYOUT, FDW_ERR_NOMEM,
+ * FDW_ERR_DEVICE. */
+int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out);
+
+/* Operator application (Section 4.8: the generated entry point; the time loop
+ * of Section 4.6: stencil, then injection, inside t).
+ * Runs steps t = time_m .. time_M.  Step t computes level t+1 from levels t
+ * and t-1 into slot (t+1) mod 3, injects src[t] (dt^2 q / m at each target
+ * point) into level t+1 (into p and r for TTI) and writes rec[t][:] by
+ * interpolating level t+1 (p for TTI).  time_M = -1 selects the largest step
+ * with no out-of-range sparse access (Section 4.2: nt_src - 1, or
+ * nt_rec - 1, the smaller).  Splitting a run into consecutive applies gives
+ * the same result as one apply.  Asynchronous: work is enqueued on `stream`
+ * (a hipStream_t; NULL = the null stream) and the call returns; launch errors
+ * are reported here, execution errors at the next call or fdw_sync.
+ * Errors: FDW_ERR_ARG (range), FDW_ERR_DEVICE. */
+int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream);
+
+/* Wait for all work the operator enqueued.  Errors: FDW_ERR_DEVICE. */
+int fdw_sync(fdw_op *op);
+int fdw_operator_destroy(fdw_op *op);
+
+/* Per-kernel timing (measurement support).  When enabled, apply brackets every
+ * launch of the operator's dominant stencil kernel with a pair of HIP events on
+ * the apply stream; fdw_operator_kernel_time synchronises and returns the
+ * summed milliseconds and the number of launches since the last reset.
+ * Errors: FDW_ERR_ARG, FDW_ERR_DEVICE. */
+int fdw_operator_set_timing(fdw_op *op, int enable);
+int fdw_operator_kernel_time(fdw_op *op, double *total_ms, int64_t *launches, int reset);
+
+/* Description of the launch plan apply will use (kernel name, tile sizes,
+ * algorithmic bytes per grid point per step of the dominant kernel).
+ * Writes a NUL-terminated string of at most buflen bytes.  Errors: FDW_ERR_ARG. */
+int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_bytes_per_point);
+
+/* Largest stable dt for the leapfrog scheme at this order (von Neumann bound
+ * of the order-so Laplacian: dt <= 2 / (v_eff sqrt(sum_a lambda_so / h_a^2)),
+ * with equal spacing hmin on every axis; v_eff = vmax for ISO and
+ * vmax sqrt(1 + 2 eps_max) for TTI).  Returns a negative value on bad input. */
+double fdw_stable_dt(int kind, int ndim, int space_order, double vmax, double eps_max, double hmin);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *fdw_last_error(void);
+
+/* Library version string. */
+const char *fdw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDW_H */

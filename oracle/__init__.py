@@ -119,6 +119,11 @@ def _field(grid, a):
     return a
 
 
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().or_num_threads())
+
+
 def fd_weights(so: int, deriv: int) -> np.ndarray:
     """Weights w[0..R] of the centred stencil of order so for d^deriv/dx^deriv."""
     w = np.zeros(so // 2 + 1)

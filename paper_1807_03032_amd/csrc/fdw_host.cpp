@@ -1,0 +1,825 @@
+// Host implementation of the fdw C ABI (include/fdw.h): handle objects,
+// argument validation, layout arithmetic, coefficient and damping tables,
+// sparse-point preprocessing and the per-step launch sequence.
+//
+// Paper: arXiv 1807.03032.  Grid / Function / TimeFunction /
+// SparseTimeFunction follow Section 3.1; domain/halo/padding Section 3.6;
+// interpolation and injection Section 3.3 (eq. interp, Listing finject);
+// the operator and its time loop Sections 4 and 4.6.
+#include "fdw.h"
+#include "fdw_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace fdw;
+
+// ---------------------------------------------------------------------------
+// Error reporting: thread-local message, status codes, no exceptions out.
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+static int fail_hip(hipError_t e, const char *where) {
+    return fail(FDW_ERR_DEVICE, "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+}
+
+#define FDW_GUARD_BEGIN try {
+#define FDW_GUARD_END                                                   \
+    }                                                                   \
+    catch (const std::bad_alloc &) {                                    \
+        return fail(FDW_ERR_NOMEM, "host allocation failed");           \
+    }                                                                   \
+    catch (...) {                                                       \
+        return fail(FDW_ERR_ARG, "unexpected internal exception");      \
+    }
+
+// ---------------------------------------------------------------------------
+// Objects
+// ---------------------------------------------------------------------------
+struct fdw_grid {
+    int ndim;
+    int64_t shape[3];  // as given: (x, y, z) or (x, z)
+    double extent[3], origin[3], h[3];
+    int refs = 0;      // live handles built on this grid
+};
+
+struct fdw_func {
+    fdw_grid *grid;
+    std::string name;
+    float *d;
+    int64_t nelem;
+    int so;
+    fdw_layout lay;
+    int refs = 0;
+};
+
+struct fdw_tfunc {
+    fdw_grid *grid;
+    std::string name;
+    float *d;
+    int64_t nelem;
+    int so;
+    int time_order;
+    fdw_layout lay;
+    int refs = 0;
+};
+
+struct fdw_sparse {
+    fdw_grid *grid;
+    std::string name;
+    int npoint, nt;
+    float *data;                      // caller's [nt][npoint]
+    std::vector<int64_t> base;        // [npoint][ndim] grid indices
+    std::vector<double> w;            // [npoint][2^ndim] weights
+    int refs = 0;
+};
+
+struct fdw_op {
+    fdw_op_desc d;
+    int ndim, R;
+    fdw_layout lay;
+    Geom geom;
+    Coefs coefs;
+    float dt2;
+    IsoVariant iso_v = IsoVariant::Naive;
+    TtiVariant tti_v = TtiVariant::Naive;
+    // library-owned device memory
+    float *d_eta = nullptr;           // eta_x | eta_y | eta_z (times dt/2)
+    float *d_stage = nullptr;         // TTI: gp | gr (each elems_per_slot)
+    int64_t *d_src_base = nullptr, *d_rec_base = nullptr;
+    float *d_src_w = nullptr, *d_rec_w = nullptr;
+    // host copies of the fused-source description
+    FusedSrc fsrc_template;
+    bool src_fused = false;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;  // pairs
+    size_t ev_used = 0;
+    double acc_ms = 0.0;
+    int64_t acc_launches = 0;
+    hipStream_t last_stream = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// Layout (Section 3.6: domain, halo, padding)
+// ---------------------------------------------------------------------------
+static bool valid_so(int so) { return so >= 2 && so <= FDW_MAX_SO && (so % 2) == 0; }
+
+static void compute_layout(const fdw_grid *g, int so, fdw_layout *L) {
+    const int R = so / 2;
+    std::memset(L, 0, sizeof(*L));
+    L->ndim = g->ndim;
+    L->halo = R;
+    for (int a = 0; a < g->ndim; ++a) L->shape[a] = g->shape[a];
+    const int64_t nx = g->shape[0];
+    const int64_t need = FDW_X_OFFSET + nx + R;
+    L->pitch_x = (need + 31) / 32 * 32;
+    if (g->ndim == 3) {
+        L->pitch_y = g->shape[1] + 2 * R;
+        L->planes = g->shape[2] + 2 * R;
+        L->origin_offset = (int64_t)R * L->pitch_y * L->pitch_x + (int64_t)R * L->pitch_x + FDW_X_OFFSET;
+    } else {
+        L->pitch_y = g->shape[1] + 2 * R;
+        L->planes = 1;
+        L->origin_offset = (int64_t)R * L->pitch_x + FDW_X_OFFSET;
+    }
+    L->elems_per_slot = L->pitch_x * L->pitch_y * L->planes;
+    L->alignment_bytes = 256;
+}
+
+// ---------------------------------------------------------------------------
+// Finite-difference weights: closed forms of the centred Taylor stencils of
+// order so = 2R (Section 3.2, the `.dx`/`.laplace` shortcuts):
+//   W2_k = 2 (-1)^(k+1) (R!)^2 / (k^2 (R-k)! (R+k)!),  W2_0 = -2 sum_k W2_k
+//   W1_k =   (-1)^(k+1) (R!)^2 / (k   (R-k)! (R+k)!)
+// ---------------------------------------------------------------------------
+static double lfact(int n) { return std::lgamma((double)n + 1.0); }
+
+static void taylor_weights(int R, double *w1, double *w2) {
+    double s = 0.0;
+    w1[0] = 0.0;
+    for (int k = 1; k <= R; ++k) {
+        const double mag = std::exp(2.0 * lfact(R) - lfact(R - k) - lfact(R + k));
+        const double sign = (k % 2) ? 1.0 : -1.0;
+        w1[k] = sign * mag / k;
+        w2[k] = 2.0 * sign * mag / ((double)k * k);
+        s += w2[k];
+    }
+    w2[0] = -2.0 * s;
+}
+
+// max over the Nyquist band of the symbol of -d2/dx2 (unit spacing)
+static double laplace_symbol_max(int R) {
+    double w1[kMaxR + 1], w2[kMaxR + 1];
+    taylor_weights(R, w1, w2);
+    double best = 0.0;
+    for (int j = 0; j <= 2048; ++j) {
+        const double th = M_PI * j / 2048.0;
+        double s = -w2[0];
+        for (int k = 1; k <= R; ++k) s -= 2.0 * w2[k] * std::cos(k * th);
+        best = std::max(best, s);
+    }
+    return best;
+}
+
+static double stable_dt_axes(int kind, int ndim, int so, double vmax, double eps_max, const double *h) {
+    if ((kind != FDW_ISO && kind != FDW_TTI) || (ndim != 2 && ndim != 3) || !valid_so(so) || !(vmax > 0.0) ||
+        !(eps_max >= 0.0))
+        return -1.0;
+    const double lam = laplace_symbol_max(so / 2);
+    double sum = 0.0;
+    for (int a = 0; a < ndim; ++a) {
+        if (!(h[a] > 0.0)) return -1.0;
+        sum += lam / (h[a] * h[a]);
+    }
+    const double veff = kind == FDW_TTI ? vmax * std::sqrt(1.0 + 2.0 * eps_max) : vmax;
+    return 2.0 / (veff * std::sqrt(sum));
+}
+
+// ---------------------------------------------------------------------------
+// Public ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *fdw_last_error(void) { return g_last_error.c_str(); }
+const char *fdw_version(void) { return "fdw 0.1 (gfx950)"; }
+
+double fdw_stable_dt(int kind, int ndim, int space_order, double vmax, double eps_max, double hmin) {
+    const double h[3] = {hmin, hmin, hmin};
+    return stable_dt_axes(kind, ndim, space_order, vmax, eps_max, h);
+}
+
+int fdw_grid_create(int ndim, const int64_t *shape, const double *extent, const double *origin,
+                    fdw_grid **out) {
+    FDW_GUARD_BEGIN
+    if (!out) return fail(FDW_ERR_ARG, "grid_create: out is NULL");
+    if (ndim != 2 && ndim != 3) return fail(FDW_ERR_ARG, "grid_create: ndim must be 2 or 3 (got %d)", ndim);
+    if (!shape || !extent) return fail(FDW_ERR_ARG, "grid_create: shape/extent is NULL");
+    for (int a = 0; a < ndim; ++a) {
+        if (shape[a] < 2 || shape[a] > (1 << 20))
+            return fail(FDW_ERR_ARG, "grid_create: shape[%d] = %lld out of range [2, 2^20]", a,
+                        (long long)shape[a]);
+        if (!(extent[a] > 0.0) || !std::isfinite(extent[a]))
+            return fail(FDW_ERR_ARG, "grid_create: extent[%d] must be positive", a);
+        if (origin && !std::isfinite(origin[a])) return fail(FDW_ERR_ARG, "grid_create: origin[%d] not finite", a);
+    }
+    fdw_grid *g = new fdw_grid();
+    g->ndim = ndim;
+    for (int a = 0; a < 3; ++a) {
+        g->shape[a] = a < ndim ? shape[a] : 1;
+        g->extent[a] = a < ndim ? extent[a] : 0.0;
+        g->origin[a] = (a < ndim && origin) ? origin[a] : 0.0;
+        g->h[a] = a < ndim ? extent[a] / (double)(shape[a] - 1) : 1.0;
+    }
+    *out = g;
+    return FDW_OK;
+    FDW_GUARD_END
+}
+
+int fdw_grid_destroy(fdw_grid *grid) {
+    if (!grid) return FDW_OK;
+    if (grid->refs > 0) return fail(FDW_ERR_STATE, "grid_destroy: %d handles still use this grid", grid->refs);
+    delete grid;
+    return FDW_OK;
+}
+
+int fdw_field_layout(const fdw_grid *grid, int space_order, fdw_layout *out) {
+    if (!grid || !out) return fail(FDW_ERR_ARG, "field_layout: NULL argument");
+    if (!valid_so(space_order)) return fail(FDW_ERR_ARG, "field_layout: space_order %d not even in [2,16]", space_order);
+    compute_layout(grid, space_order, out);
+    return FDW_OK;
+}
+
+static int check_buffer(const char *what, const void *p, int64_t nelem, int64_t need) {
+    if (!p) return fail(FDW_ERR_ARG, "%s: device pointer is NULL", what);
+    if (((uintptr_t)p) % 256 != 0) return fail(FDW_ERR_LAYOUT, "%s: pointer not 256-byte aligned", what);
+    if (nelem < need)
+        return fail(FDW_ERR_LAYOUT, "%s: buffer holds %lld floats, layout needs %lld", what, (long long)nelem,
+                    (long long)need);
+    return FDW_OK;
+}
+
+int fdw_function_bind(fdw_grid *grid, const char *name, float *dptr, int64_t nelem, int space_order,
+                      fdw_func **out) {
+    FDW_GUARD_BEGIN
+    if (!grid || !out) return fail(FDW_ERR_ARG, "function_bind: NULL grid/out");
+    if (!valid_so(space_order)) return fail(FDW_ERR_ARG, "function_bind: space_order %d not even in [2,16]", space_order);
+    fdw_layout L;
+    compute_layout(grid, space_order, &L);
+    int st = check_buffer("function_bind", dptr, nelem, L.elems_per_slot);
+    if (st) return st;
+    fdw_func *f = new fdw_func();
+    f->grid = grid;
+    f->name = name ? name : "";
+    f->d = dptr;
+    f->nelem = nelem;
+    f->so = space_order;
+    f->lay = L;
+    grid->refs++;
+    *out = f;
+    return FDW_OK;
+    FDW_GUARD_END
+}
+
+int fdw_function_destroy(fdw_func *f) {
+    if (!f) return FDW_OK;
+    if (f->refs > 0) return fail(FDW_ERR_STATE, "function_destroy: used by %d operators", f->refs);
+    f->grid->refs--;
+    delete f;
+    return FDW_OK;
+}
+
+int fdw_timefunction_bind(fdw_grid *grid, const char *name, float *dptr, int64_t nelem, int space_order,
+                          int time_order, fdw_tfunc **out) {
+    FDW_GUARD_BEGIN
+    if (!grid || !out) return fail(FDW_ERR_ARG, "timefunction_bind: NULL grid/out");
+    if (!valid_so(space_order))
+        return fail(FDW_ERR_ARG, "timefunction_bind: space_order %d not even in [2,16]", space_order);
+    if (time_order != 2) return fail(FDW_ERR_ARG, "timefunction_bind: time_order must be 2 (got %d)", time_order);
+    fdw_layout L;
+    compute_layout(grid, space_order, &L);
+    int st = check_buffer("timefunction_bind", dptr, nelem, 3 * L.elems_per_slot);
+    if (st) return st;
+    fdw_tfunc *f = new fdw_tfunc();
+    f->grid = grid;
+    f->name = name ? name : "";
+    f->d = dptr;
+    f->nelem = nelem;
+    f->so = space_order;
+    f->time_order = time_order;
+    f->lay = L;
+    grid->refs++;
+    *out = f;
+    return FDW_OK;
+    FDW_GUARD_END
+}
+
+int fdw_timefunction_destroy(fdw_tfunc *f) {
+    if (!f) return FDW_OK;
+    if (f->refs > 0) return fail(FDW_ERR_STATE, "timefunction_destroy: used by %d operators", f->refs);
+    f->grid->refs--;
+    delete f;
+    return FDW_OK;
+}
+
+int fdw_sparse_bind(fdw_grid *grid, const char *name, int npoint, int nt, const double *coords_host,
+                    float *ddata, fdw_sparse **out) {
+    FDW_GUARD_BEGIN
+    if (!grid || !out) return fail(FDW_ERR_ARG, "sparse_bind: NULL grid/out");
+    if (npoint < 0 || nt < 0) return fail(FDW_ERR_ARG, "sparse_bind: negative npoint/nt");
+    if (npoint > 0 && (!coords_host || !ddata)) return fail(FDW_ERR_ARG, "sparse_bind: NULL coords/data");
+    if (npoint > 0 && nt < 1) return fail(FDW_ERR_ARG, "sparse_bind: nt must be >= 1");
+    const int nd = grid->ndim, nc = 1 << nd;
+    std::vector<int64_t> base((size_t)npoint * nd);
+    std::vector<double> w((size_t)npoint * nc);
+    for (int p = 0; p < npoint; ++p) {
+        double f[3];
+        for (int a = 0; a < nd; ++a) {
+            const double c = coords_host[(size_t)p * nd + a];
+            const double xi = (c - grid->origin[a]) / grid->h[a];
+            if (!(xi >= 0.0 && xi <= (double)(grid->shape[a] - 1)))
+                return fail(FDW_ERR_DOMAIN, "sparse_bind(%s): point %d axis %d coordinate %g outside [%g, %g]",
+                            name ? name : "", p, a, c, grid->origin[a],
+                            grid->origin[a] + grid->h[a] * (double)(grid->shape[a] - 1));
+            int64_t b = (int64_t)std::floor(xi);
+            b = std::min<int64_t>(b, grid->shape[a] - 2);
+            base[(size_t)p * nd + a] = b;
+            f[a] = xi - (double)b;
+        }
+        for (int c = 0; c < nc; ++c) {
+            double ww = 1.0;
+            for (int a = 0; a < nd; ++a) ww *= ((c >> a) & 1) ? f[a] : (1.0 - f[a]);
+            w[(size_t)p * nc + c] = ww;
+        }
+    }
+    fdw_sparse *s = new fdw_sparse();
+    s->grid = grid;
+    s->name = name ? name : "";
+    s->npoint = npoint;
+    s->nt = nt;
+    s->data = ddata;
+    s->base.swap(base);
+    s->w.swap(w);
+    grid->refs++;
+    *out = s;
+    return FDW_OK;
+    FDW_GUARD_END
+}
+
+int fdw_sparse_destroy(fdw_sparse *s) {
+    if (!s) return FDW_OK;
+    if (s->refs > 0) return fail(FDW_ERR_STATE, "sparse_destroy: used by %d operators", s->refs);
+    s->grid->refs--;
+    delete s;
+    return FDW_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Operator construction helpers
+// ---------------------------------------------------------------------------
+static void release_device(fdw_op *op) {
+    if (op->d_eta) (void)hipFree(op->d_eta);
+    if (op->d_stage) (void)hipFree(op->d_stage);
+    if (op->d_src_base) (void)hipFree(op->d_src_base);
+    if (op->d_rec_base) (void)hipFree(op->d_rec_base);
+    if (op->d_src_w) (void)hipFree(op->d_src_w);
+    if (op->d_rec_w) (void)hipFree(op->d_rec_w);
+    for (hipEvent_t e : op->ev_pool) (void)hipEventDestroy(e);
+    op->ev_pool.clear();
+    op->d_eta = op->d_stage = op->d_src_w = op->d_rec_w = nullptr;
+    op->d_src_base = op->d_rec_base = nullptr;
+}
+
+// element offset of grid point (x, y, z) (2D: y ignored, idx[1] is z)
+static int64_t element_offset(const fdw_op *op, const int64_t *idx) {
+    if (op->ndim == 3) return op->geom.off0 + idx[2] * op->geom.sz + idx[1] * op->geom.sy + idx[0];
+    return op->geom.off0 + idx[1] * op->geom.sz + idx[0];
+}
+
+static int upload_sparse(fdw_op *op, const fdw_sparse *s, double scale, int64_t **d_base, float **d_w) {
+    const int nc = 1 << op->ndim;
+    std::vector<int64_t> off(s->npoint);
+    std::vector<float> w((size_t)s->npoint * nc);
+    for (int p = 0; p < s->npoint; ++p) {
+        off[p] = element_offset(op, &s->base[(size_t)p * op->ndim]);
+        for (int c = 0; c < nc; ++c) w[(size_t)p * nc + c] = (float)(scale * s->w[(size_t)p * nc + c]);
+    }
+    hipError_t e = hipMalloc((void **)d_base, sizeof(int64_t) * std::max(1, s->npoint));
+    if (e != hipSuccess) return fail(FDW_ERR_NOMEM, "operator_create: hipMalloc sparse base: %s", hipGetErrorString(e));
+    e = hipMalloc((void **)d_w, sizeof(float) * std::max<size_t>(1, w.size()));
+    if (e != hipSuccess) return fail(FDW_ERR_NOMEM, "operator_create: hipMalloc sparse weights: %s", hipGetErrorString(e));
+    if (s->npoint > 0) {
+        e = hipMemcpy(*d_base, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(*d_w, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail_hip(e, "operator_create: sparse upload");
+    }
+    return FDW_OK;
+}
+
+static int check_func(const char *what, const fdw_func *f, const fdw_grid *g, int so) {
+    if (!f) return fail(FDW_ERR_ARG, "operator_create: %s is required", what);
+    if (f->grid != g) return fail(FDW_ERR_ARG, "operator_create: %s is bound on another grid", what);
+    if (f->so != so)
+        return fail(FDW_ERR_LAYOUT, "operator_create: %s bound at space order %d, operator uses %d", what, f->so, so);
+    return FDW_OK;
+}
+
+static int check_tfunc(const char *what, const fdw_tfunc *f, const fdw_grid *g, int so) {
+    if (!f) return fail(FDW_ERR_ARG, "operator_create: %s is required", what);
+    if (f->grid != g) return fail(FDW_ERR_ARG, "operator_create: %s is bound on another grid", what);
+    if (f->so != so)
+        return fail(FDW_ERR_LAYOUT, "operator_create: %s bound at space order %d, operator uses %d", what, f->so, so);
+    return FDW_OK;
+}
+
+static void pick_variants(fdw_op *op) {
+    // FDW_KERNEL=naive forces the one-thread-per-point kernels (A/B checks).
+    const char *k = std::getenv("FDW_KERNEL");
+    const bool naive = k && std::strcmp(k, "naive") == 0;
+    op->iso_v = naive ? IsoVariant::Naive : IsoVariant::Stream;
+    op->tti_v = naive ? TtiVariant::Naive : TtiVariant::Stream;
+}
+
+extern "C" {
+
+int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
+    FDW_GUARD_BEGIN
+    if (!desc || !out) return fail(FDW_ERR_ARG, "operator_create: NULL desc/out");
+    const fdw_op_desc &d = *desc;
+    if (d.kind != FDW_ISO && d.kind != FDW_TTI) return fail(FDW_ERR_ARG, "operator_create: unknown kind %d", d.kind);
+    if (!valid_so(d.space_order))
+        return fail(FDW_ERR_ARG, "operator_create: space_order %d not even in [2,16]", d.space_order);
+    if (!d.u) return fail(FDW_ERR_ARG, "operator_create: wavefield u/p is required");
+    fdw_grid *g = d.u->grid;
+    const int so = d.space_order;
+    int st = check_tfunc("u/p", d.u, g, so);
+    if (!st) st = check_func("m", d.m, g, so);
+    if (st) return st;
+    if (d.kind == FDW_TTI) {
+        if ((st = check_tfunc("r", d.r, g, so))) return st;
+        if ((st = check_func("eps", d.eps, g, so))) return st;
+        if ((st = check_func("delta", d.delta, g, so))) return st;
+        if ((st = check_func("theta", d.theta, g, so))) return st;
+        if (g->ndim == 3 && (st = check_func("phi", d.phi, g, so))) return st;
+        if (d.r == d.u) return fail(FDW_ERR_ARG, "operator_create: p and r must be distinct TimeFunctions");
+    } else if (d.r) {
+        return fail(FDW_ERR_ARG, "operator_create: r must be NULL for the isotropic operator");
+    }
+    if (d.src && d.src->grid != g) return fail(FDW_ERR_ARG, "operator_create: src bound on another grid");
+    if (d.rec && d.rec->grid != g) return fail(FDW_ERR_ARG, "operator_create: rec bound on another grid");
+    if (!(d.dt > 0.0) || !std::isfinite(d.dt)) return fail(FDW_ERR_ARG, "operator_create: dt must be positive");
+    if (!(d.vmax > 0.0) || !std::isfinite(d.vmax)) return fail(FDW_ERR_ARG, "operator_create: vmax must be positive");
+    if (d.nbl < 0) return fail(FDW_ERR_ARG, "operator_create: nbl must be >= 0");
+    const double rc = d.damp_rc == 0.0 ? 1e-3 : d.damp_rc;
+    if (!(rc > 0.0 && rc < 1.0)) return fail(FDW_ERR_ARG, "operator_create: damp_rc must be in (0, 1)");
+    const double eps_max = d.kind == FDW_TTI ? d.eps_max : 0.0;
+    if (!(eps_max >= 0.0)) return fail(FDW_ERR_ARG, "operator_create: eps_max must be >= 0");
+    const double dtmax = stable_dt_axes(d.kind, g->ndim, so, d.vmax, eps_max, g->h);
+    if (d.dt > dtmax)
+        return fail(FDW_ERR_UNSTABLE, "operator_create: dt = %g exceeds the stability bound %g", d.dt, dtmax);
+
+    fdw_op *op = new fdw_op();
+    op->d = d;
+    op->d.damp_rc = rc;
+    op->ndim = g->ndim;
+    op->R = so / 2;
+    compute_layout(g, so, &op->lay);
+    const fdw_layout &L = op->lay;
+    Geom &G = op->geom;
+    G.nx = (int)g->shape[0];
+    if (g->ndim == 3) {
+        G.ny = (int)g->shape[1];
+        G.nz = (int)g->shape[2];
+        G.sy = L.pitch_x;
+        G.sz = L.pitch_x * L.pitch_y;
+    } else {
+        G.ny = 1;
+        G.nz = (int)g->shape[1];
+        G.sy = 0;
+        G.sz = L.pitch_x;
+    }
+    G.off0 = L.origin_offset;
+    op->dt2 = (float)(d.dt * d.dt);
+
+    // FD coefficients (double, rounded once)
+    double w1[kMaxR + 1], w2[kMaxR + 1];
+    taylor_weights(op->R, w1, w2);
+    std::memset(&op->coefs, 0, sizeof(op->coefs));
+    const int axis_of[3] = {0, g->ndim == 3 ? 1 : 2, 2};  // grid axis -> coefficient slot
+    double c0 = 0.0;
+    for (int a = 0; a < g->ndim; ++a) {
+        const int slot = axis_of[a];
+        const double h = g->h[a];
+        for (int k = 0; k <= op->R; ++k) {
+            op->coefs.w2[slot][k] = (float)(w2[k] / (h * h));
+            op->coefs.w1[slot][k] = (float)(w1[k] / h);
+        }
+        c0 += w2[0] / (h * h);
+    }
+    op->coefs.c0 = (float)c0;
+
+    // damping tables eta_a(i) * dt / 2 (quadratic profile inside the layer)
+    const int64_t nx = G.nx, ny = G.ny, nz = G.nz;
+    std::vector<float> eta((size_t)(nx + ny + nz), 0.0f);
+    auto fill_axis = [&](float *dst, int64_t n, double h) {
+        for (int64_t i = 0; i < n; ++i) {
+            double v = 0.0;
+            if (d.nbl > 0) {
+                const int64_t dist = std::max<int64_t>({(int64_t)d.nbl - i, i - (n - 1 - d.nbl), 0});
+                const double emax = 3.0 * d.vmax * std::log(1.0 / rc) / (2.0 * d.nbl * h);
+                const double r = (double)dist / (double)d.nbl;
+                v = emax * r * r * d.dt / 2.0;
+            }
+            dst[i] = (float)v;
+        }
+    };
+    fill_axis(eta.data(), nx, g->h[0]);
+    if (g->ndim == 3) {
+        fill_axis(eta.data() + nx, ny, g->h[1]);
+        fill_axis(eta.data() + nx + ny, nz, g->h[2]);
+    } else {
+        fill_axis(eta.data() + nx + ny, nz, g->h[1]);  // the single y entry stays 0
+    }
+    hipError_t e = hipMalloc((void **)&op->d_eta, sizeof(float) * eta.size());
+    if (e != hipSuccess) {
+        release_device(op);
+        delete op;
+        return fail(FDW_ERR_NOMEM, "operator_create: hipMalloc damping: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(op->d_eta, eta.data(), sizeof(float) * eta.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        release_device(op);
+        delete op;
+        return fail_hip(e, "operator_create: damping upload");
+    }
+
+    // sparse preprocessing: element offsets and float weights
+    if (d.src) {
+        st = upload_sparse(op, d.src, d.dt * d.dt, &op->d_src_base, &op->d_src_w);
+        if (!st && d.src->npoint <= kMaxFusedSrc) {
+            op->src_fused = true;
+            FusedSrc &F = op->fsrc_template;
+            std::memset(&F, 0, sizeof(F));
+            F.n = d.src->npoint;
+            for (int s = 0; s < F.n; ++s) {
+                const int64_t *b = &d.src->base[(size_t)s * g->ndim];
+                F.bx[s] = (int)b[0];
+                F.by[s] = g->ndim == 3 ? (int)b[1] : 0;
+                F.bz[s] = (int)b[g->ndim - 1];
+                for (int c = 0; c < (1 << g->ndim); ++c)
+                    F.w[s][c] = (float)(d.dt * d.dt * d.src->w[(size_t)s * (1 << g->ndim) + c]);
+            }
+        }
+    }
+    if (!st && d.rec) st = upload_sparse(op, d.rec, 1.0, &op->d_rec_base, &op->d_rec_w);
+    if (st) {
+        release_device(op);
+        delete op;
+        return st;
+    }
+
+    // TTI stage buffers (zero halo: g vanishes outside the domain)
+    if (d.kind == FDW_TTI) {
+        const size_t bytes = sizeof(float) * (size_t)L.elems_per_slot * 2;
+        e = hipMalloc((void **)&op->d_stage, bytes);
+        if (e == hipSuccess) e = hipMemset(op->d_stage, 0, bytes);
+        if (e != hipSuccess) {
+            release_device(op);
+            delete op;
+            return fail(FDW_ERR_NOMEM, "operator_create: TTI stage buffers: %s", hipGetErrorString(e));
+        }
+    }
+
+    // zero the halo of every wavefield slot
+    std::vector<fdw_tfunc *> tfs{d.u};
+    if (d.kind == FDW_TTI) tfs.push_back(d.r);
+    for (fdw_tfunc *tf : tfs)
+        for (int sl = 0; sl < 3; ++sl) {
+            e = launch_zero_halo(op->ndim, G, op->R, L.pitch_x, L.pitch_y, L.planes,
+                                 tf->d + (int64_t)sl * L.elems_per_slot, nullptr);
+            if (e != hipSuccess) break;
+        }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        release_device(op);
+        delete op;
+        return fail_hip(e, "operator_create: zero halo");
+    }
+
+    pick_variants(op);
+    // reference counts keep bound handles alive while the operator exists
+    d.u->refs++;
+    if (d.r) d.r->refs++;
+    for (fdw_func *f : {d.m, d.eps, d.delta, d.theta, d.phi})
+        if (f) f->refs++;
+    if (d.src) d.src->refs++;
+    if (d.rec) d.rec->refs++;
+    *out = op;
+    return FDW_OK;
+    FDW_GUARD_END
+}
+
+int fdw_operator_destroy(fdw_op *op) {
+    if (!op) return FDW_OK;
+    const fdw_op_desc &d = op->d;
+    d.u->refs--;
+    if (d.r) d.r->refs--;
+    for (fdw_func *f : {d.m, d.eps, d.delta, d.theta, d.phi})
+        if (f) f->refs--;
+    if (d.src) d.src->refs--;
+    if (d.rec) d.rec->refs--;
+    release_device(op);
+    delete op;
+    return FDW_OK;
+}
+
+static int timing_event_pair(fdw_op *op, hipEvent_t *a, hipEvent_t *b) {
+    while (op->ev_used + 2 > op->ev_pool.size()) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return fail_hip(err, "timing: hipEventCreate");
+        op->ev_pool.push_back(e);
+    }
+    *a = op->ev_pool[op->ev_used];
+    *b = op->ev_pool[op->ev_used + 1];
+    op->ev_used += 2;
+    return FDW_OK;
+}
+
+int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
+    FDW_GUARD_BEGIN
+    if (!op) return fail(FDW_ERR_ARG, "operator_apply: NULL op");
+    const fdw_op_desc &d = op->d;
+    hipStream_t s = (hipStream_t)stream;
+    if (time_M == -1) {
+        int lim = -1;
+        if (d.src && d.src->npoint > 0) lim = d.src->nt;
+        if (d.rec && d.rec->npoint > 0) lim = lim < 0 ? d.rec->nt : std::min(lim, d.rec->nt);
+        if (lim < 0) return fail(FDW_ERR_ARG, "operator_apply: time_M = -1 needs a source or receiver time axis");
+        time_M = lim - 1;
+    }
+    if (time_m < 0 || time_M < time_m - 1)
+        return fail(FDW_ERR_ARG, "operator_apply: invalid range time_m = %d, time_M = %d", time_m, time_M);
+    if (d.src && d.src->npoint > 0 && time_M >= d.src->nt)
+        return fail(FDW_ERR_ARG, "operator_apply: time_M = %d beyond the %d source samples", time_M, d.src->nt);
+    if (d.rec && d.rec->npoint > 0 && time_M >= d.rec->nt)
+        return fail(FDW_ERR_ARG, "operator_apply: time_M = %d beyond the %d receiver samples", time_M, d.rec->nt);
+    const fdw_layout &L = op->lay;
+    const int64_t E = L.elems_per_slot;
+    const float *eta_x = op->d_eta, *eta_y = op->d_eta + op->geom.nx, *eta_z = op->d_eta + op->geom.nx + op->geom.ny;
+    const int nsrc = d.src ? d.src->npoint : 0;
+    const int nrec = d.rec ? d.rec->npoint : 0;
+    if (op->timing) op->last_stream = s;
+
+    SparseArgs inj{};
+    inj.npoint = nsrc;
+    inj.ncorner = 1 << op->ndim;
+    inj.base = op->d_src_base;
+    inj.w = op->d_src_w;
+    inj.cstride[0] = 1;
+    inj.cstride[1] = op->ndim == 3 ? op->geom.sy : op->geom.sz;
+    inj.cstride[2] = op->ndim == 3 ? op->geom.sz : 0;
+    inj.m = d.m->d;
+    SparseArgs itp = inj;
+    itp.npoint = nrec;
+    itp.base = op->d_rec_base;
+    itp.w = op->d_rec_w;
+    itp.m = nullptr;
+
+    for (int t = time_m; t <= time_M; ++t) {
+        const int sc = t % 3, sp = (t + 2) % 3, sn = (t + 1) % 3;
+        FusedSrc fs{};
+        if (op->src_fused && nsrc > 0) {
+            fs = op->fsrc_template;
+            fs.q = d.src->data + (int64_t)t * nsrc;
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (op->timing) {
+            int st = timing_event_pair(op, &e0, &e1);
+            if (st) return st;
+            hipError_t er = hipEventRecord(e0, s);
+            if (er != hipSuccess) return fail_hip(er, "operator_apply: hipEventRecord");
+        }
+        hipError_t e;
+        float *next_field;
+        if (d.kind == FDW_ISO) {
+            IsoArgs a{};
+            a.g = op->geom;
+            a.u_cur = d.u->d + sc * E;
+            a.u_prev = d.u->d + sp * E;
+            a.u_next = d.u->d + sn * E;
+            a.m = d.m->d;
+            a.eta_x = eta_x;
+            a.eta_y = eta_y;
+            a.eta_z = eta_z;
+            a.dt2 = op->dt2;
+            a.c = op->coefs;
+            a.src = fs;
+            e = launch_iso(op->ndim, op->R, op->iso_v, a, s);
+            next_field = a.u_next;
+        } else {
+            TtiArgs a{};
+            a.g = op->geom;
+            a.p_cur = d.u->d + sc * E;
+            a.p_prev = d.u->d + sp * E;
+            a.p_next = d.u->d + sn * E;
+            a.r_cur = d.r->d + sc * E;
+            a.r_prev = d.r->d + sp * E;
+            a.r_next = d.r->d + sn * E;
+            a.m = d.m->d;
+            a.eps = d.eps->d;
+            a.delta = d.delta->d;
+            a.theta = d.theta->d;
+            a.phi = d.phi ? d.phi->d : nullptr;
+            a.gp = op->d_stage;
+            a.gr = op->d_stage + E;
+            a.eta_x = eta_x;
+            a.eta_y = eta_y;
+            a.eta_z = eta_z;
+            a.dt2 = op->dt2;
+            a.c = op->coefs;
+            a.src = fs;
+            e = launch_tti(op->ndim, op->R, op->tti_v, a, s);
+            next_field = a.p_next;
+        }
+        if (e != hipSuccess) return fail_hip(e, "operator_apply: stencil launch");
+        if (op->timing) {
+            hipError_t er = hipEventRecord(e1, s);
+            if (er != hipSuccess) return fail_hip(er, "operator_apply: hipEventRecord");
+            op->acc_launches++;
+        }
+        if (nsrc > 0 && !op->src_fused) {
+            inj.q_row = d.src->data + (int64_t)t * nsrc;
+            inj.field = next_field;
+            if ((e = launch_inject(inj, s)) != hipSuccess) return fail_hip(e, "operator_apply: inject launch");
+            if (d.kind == FDW_TTI) {
+                inj.field = d.r->d + sn * E;
+                if ((e = launch_inject(inj, s)) != hipSuccess) return fail_hip(e, "operator_apply: inject launch");
+            }
+        }
+        if (nrec > 0) {
+            itp.field = next_field;
+            itp.rec_row = d.rec->data + (int64_t)t * nrec;
+            if ((e = launch_interp(itp, s)) != hipSuccess) return fail_hip(e, "operator_apply: interp launch");
+        }
+    }
+    return FDW_OK;
+    FDW_GUARD_END
+}
+
+int fdw_sync(fdw_op *op) {
+    if (!op) return fail(FDW_ERR_ARG, "sync: NULL op");
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail_hip(e, "sync");
+    return FDW_OK;
+}
+
+int fdw_operator_set_timing(fdw_op *op, int enable) {
+    if (!op) return fail(FDW_ERR_ARG, "set_timing: NULL op");
+    op->timing = enable != 0;
+    op->ev_used = 0;
+    op->acc_ms = 0.0;
+    op->acc_launches = 0;
+    return FDW_OK;
+}
+
+int fdw_operator_kernel_time(fdw_op *op, double *total_ms, int64_t *launches, int reset) {
+    if (!op || !total_ms || !launches) return fail(FDW_ERR_ARG, "kernel_time: NULL argument");
+    double sum = op->acc_ms;
+    for (size_t i = 0; i + 1 < op->ev_used; i += 2) {
+        hipError_t e = hipEventSynchronize(op->ev_pool[i + 1]);
+        if (e != hipSuccess) return fail_hip(e, "kernel_time: hipEventSynchronize");
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, op->ev_pool[i], op->ev_pool[i + 1]);
+        if (e != hipSuccess) return fail_hip(e, "kernel_time: hipEventElapsedTime");
+        sum += ms;
+    }
+    // fold the measured pairs so the pool can be reused
+    op->acc_ms = sum;
+    op->ev_used = 0;
+    *total_ms = sum;
+    *launches = op->acc_launches;
+    if (reset) {
+        op->acc_ms = 0.0;
+        op->acc_launches = 0;
+    }
+    return FDW_OK;
+}
+
+int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_bytes_per_point) {
+    if (!op || !buf || buflen <= 0) return fail(FDW_ERR_ARG, "describe: NULL argument");
+    const bool iso = op->d.kind == FDW_ISO;
+    const char *name = iso ? iso_kernel_name(op->ndim, op->iso_v) : tti_kernel_name(op->ndim, op->tti_v);
+    snprintf(buf, (size_t)buflen, "%s so=%d R=%d ndim=%d src=%s nsrc=%d nrec=%d", name, op->d.space_order, op->R,
+             op->ndim, op->src_fused ? "fused" : "kernel", op->d.src ? op->d.src->npoint : 0,
+             op->d.rec ? op->d.rec->npoint : 0);
+    // algorithmic HBM bytes per point per step: iso reads u^n, u^n-1, m and
+    // writes u^n+1; TTI reads p, r at two levels and m, eps, delta, theta(, phi)
+    // and writes p, r.
+    if (alg_bytes_per_point)
+        *alg_bytes_per_point = iso ? 16.0 : (op->ndim == 3 ? 44.0 : 40.0);
+    return FDW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Internal declarations shared by the host ABI (fdw_host.cpp) and the HIP
+// kernels (fdw_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdw {
+
+constexpr int kMaxR = 8;         // space order 16
+constexpr int kMaxFusedSrc = 4;  // sources injected inside the stencil kernel
+
+// Finite-difference coefficients, computed on the host in double from the
+// closed-form Taylor weights and rounded once to float.
+//   w2[a][k] = W2_k / h_a^2   (second derivative along axis a, k = 0..R)
+//   w1[a][k] = W1_k / h_a     (first derivative along axis a, k = 1..R)
+//   c0       = sum_a W2_0 / h_a^2 (centre weight of the Laplacian)
+// Axis index a: 0 = x, 1 = y, 2 = z (2D grids use 0 and 2).
+struct Coefs {
+    float w2[3][kMaxR + 1];
+    float w1[3][kMaxR + 1];
+    float c0;
+};
+
+// Up to kMaxFusedSrc point sources injected by the thread that owns each
+// target point, right after it computes the point's update.
+//   b[s]      base grid indices (x, y, z) of source s (y = 0 in 2D)
+//   w[s][c]   dt^2 * interpolation weight of corner c (bit 0: +x, bit 1: +y
+//             in 3D or +z in 2D, bit 2: +z in 3D)
+//   q         device pointer to the source samples of this step (row t)
+struct FusedSrc {
+    int n;
+    int bx[kMaxFusedSrc], by[kMaxFusedSrc], bz[kMaxFusedSrc];
+    float w[kMaxFusedSrc][8];
+    const float *q;
+};
+
+// Geometry of the padded layout (all fields of one operator share it).
+struct Geom {
+    int nx, ny, nz;    // domain points (ny = 1 in 2D)
+    int64_t sy, sz;    // strides of +y and +z in elements (2D: sy = 0, sz = pitch_x)
+    int64_t off0;      // element offset of logical (0, 0, 0)
+};
+
+struct IsoArgs {
+    Geom g;
+    const float *u_cur, *u_prev, *m;
+    float *u_next;
+    const float *eta_x, *eta_y, *eta_z;  // damping per axis, already times dt/2
+    float dt2;
+    Coefs c;
+    FusedSrc src;
+};
+
+struct TtiArgs {
+    Geom g;
+    const float *p_cur, *p_prev, *r_cur, *r_prev;
+    float *p_next, *r_next;
+    const float *m, *eps, *delta, *theta, *phi;
+    float *gp, *gr;  // stage buffers: rotated gradients n . grad p, n . grad r
+    const float *eta_x, *eta_y, *eta_z;
+    float dt2;
+    Coefs c;
+    FusedSrc src;
+};
+
+struct SparseArgs {
+    int npoint;
+    int ncorner;                 // 4 (2D) or 8 (3D)
+    const int64_t *base;         // [npoint] element offset of corner 0
+    const float *w;              // [npoint][ncorner] weights (times scale for injection)
+    int64_t cstride[3];          // offsets of +axis0, +axis1, +axis2 corners
+    const float *m;              // injection: divisor field; NULL for interpolation
+    float *field;                // injection target / interpolation source
+    const float *q_row;          // injection: samples of this step
+    float *rec_row;              // interpolation: output row of this step
+};
+
+// Kernel variants selectable per operator (FDW_KERNEL environment knob).
+enum class IsoVariant { Naive = 0, Stream = 1 };
+enum class TtiVariant { Naive = 0, Stream = 1 };
+
+// Launchers (fdw_kernels.hip).  Each returns the hipError_t of its launch.
+hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream_t s);
+hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s);
+hipError_t launch_inject(const SparseArgs &a, hipStream_t s);
+hipError_t launch_interp(const SparseArgs &a, hipStream_t s);
+hipError_t launch_zero_halo(int ndim, const Geom &g, int R, int64_t pitch_x, int64_t pitch_y,
+                            int64_t planes, float *base, hipStream_t s);
+
+// Human-readable description of the launch plan of the dominant kernel.
+const char *iso_kernel_name(int ndim, IsoVariant v);
+const char *tti_kernel_name(int ndim, TtiVariant v);
+
+}  // namespace fdw

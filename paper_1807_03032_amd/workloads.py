@@ -68,9 +68,10 @@ def smooth_field(shape_xyz, seed: int, lo: float, hi: float, sigma_pts: float = 
     wmin, wmax = float(w.min()), float(w.max())
     w = (w - wmin) / (wmax - wmin) if wmax > wmin else np.zeros_like(w)
     w = lo + (hi - lo) * w
-    # multilinear upsampling, one axis at a time
+    # multilinear upsampling, one axis at a time, fastest (smallest result) first
     out = w
-    for ax, n in enumerate(shape):
+    for ax in reversed(range(len(shape))):
+        n = shape[ax]
         pos = np.arange(n, dtype=np.float64) / step
         pos = np.minimum(pos, out.shape[ax] - 1)
         i0 = np.minimum(np.floor(pos).astype(np.int64), out.shape[ax] - 2)
@@ -227,7 +228,8 @@ def small_problem(kind: str, shape, so: int, nt: int, seed: int = 0, nsrc: int =
     ns = src_coords.shape[0]
     if f0 is None:
         f0 = vrange[0] / (8.0 * h)  # about 8 points per wavelength at the peak frequency
-    src = np.stack([ricker(f0, (1.0 + 0.2 * k) / f0, dt, nt) for k in range(ns)], axis=1)
+    src = (np.stack([ricker(f0, (1.0 + 0.2 * k) / f0, dt, nt) for k in range(ns)], axis=1) if ns
+           else np.zeros((nt, 0)))
     if rec_coords is None:
         rec_coords = rng.uniform(0.0, 1.0, size=(nrec, ndim)) * np.asarray(extent)
     return Problem(f"small_{kind}_{'x'.join(map(str, shape))}_so{so}", kind, shape, extent, (0.0,) * ndim,

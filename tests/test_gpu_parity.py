@@ -1,0 +1,242 @@
+"""GPU parity: the HIP operators (called through the C ABI) against the FP64
+oracle on identical seeded inputs.
+
+Bar (written here, from the target accuracy of the operators): relative L2
+error <= 1e-4, computed in FP64, separately for each of the last two time
+levels of every wavefield over the domain and for the receiver traces.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_03032_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1807_03032_amd import fdw
+    fdw.load()
+    return torch.device("cuda:0")
+
+
+def gpu_run(prob, dev, splits=None, u_init=None, time_M=None):
+    from paper_1807_03032_amd import fdw
+    shot = fdw.Shot(prob, dev, u_init=u_init)
+    try:
+        if splits:
+            lo = 0
+            for hi in splits + [prob.nt - 1]:
+                shot.apply(lo, hi)
+                lo = hi + 1
+        elif time_M == -1:
+            shot.apply(0, -1)
+        else:
+            shot.apply(0, prob.nt - 1)
+        f = shot.fields(prob.nt - 1)
+        tr = shot.traces()
+        desc = fdw.fdw_operator_describe(shot.op)[0]
+    finally:
+        shot.close()
+    return f, tr, desc
+
+
+def oracle_run(prob, u_init=None):
+    g = oracle.Grid(prob.shape, prob.extent, prob.origin, so=prob.so, dt=prob.dt, nbl=prob.nbl, vmax=prob.vmax,
+                    rc=prob.rc)
+    f = prob.fields
+    if prob.kind == "iso":
+        ui = (u_init or {}).get("u", (None, None))
+        up, uc, rec = oracle.iso_run(g, f["m"], prob.nt, ui[0], ui[1], src_coords=prob.src_coords, src=prob.src,
+                                     rec_coords=prob.rec_coords)
+        return {"u": (up, uc)}, rec
+    pi = (u_init or {}).get("p", (None, None))
+    ri = (u_init or {}).get("r", (None, None))
+    pp, pc, rp, rc, rec = oracle.tti_run(g, f["m"], f["eps"], f["delta"], f["theta"], f.get("phi"), prob.nt, pi[0],
+                                         pi[1], ri[0], ri[1], src_coords=prob.src_coords, src=prob.src,
+                                         rec_coords=prob.rec_coords)
+    return {"p": (pp, pc), "r": (rp, rc)}, rec
+
+
+def check(prob, gf, gtr, of, otr, tol=TOL):
+    errs = {}
+    for nm, (ref_prev, ref_cur) in of.items():
+        errs[f"{nm}_prev"] = rel_l2(gf[nm][0], ref_prev)
+        errs[f"{nm}_cur"] = rel_l2(gf[nm][1], ref_cur)
+    if otr.size:
+        errs["rec"] = rel_l2(gtr, otr)
+    say(prob.name, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, (prob.name, k, v)
+    for nm, (ref_prev, ref_cur) in of.items():
+        assert np.linalg.norm(ref_cur) > 0, "degenerate case: reference field is zero"
+    return errs
+
+
+# ---------------------------------------------------------------- small grids
+@pytest.mark.parametrize("so", [2, 4, 8, 12, 16])
+@pytest.mark.parametrize("shape", [(67, 45), (37, 29, 23)])
+def test_iso_small(torch_dev, shape, so):
+    prob = W.small_problem("iso", shape, so, nt=40, seed=so, nsrc=2, nrec=16, nbl=4)
+    say("iso", shape, so)
+    gf, gtr, desc = gpu_run(prob, torch_dev)
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+
+
+@pytest.mark.parametrize("so", [4, 8, 12, 16])
+@pytest.mark.parametrize("shape", [(53, 41), (33, 27, 21)])
+def test_tti_small(torch_dev, shape, so):
+    prob = W.small_problem("tti", shape, so, nt=30, seed=50 + so, nsrc=1, nrec=12, nbl=4)
+    say("tti", shape, so)
+    gf, gtr, desc = gpu_run(prob, torch_dev)
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+
+
+@pytest.mark.parametrize("kind", ["iso", "tti"])
+def test_many_colliding_sources(torch_dev, kind):
+    """More sources than the fused path holds (atomic injection), several in one cell."""
+    shape = (41, 35, 30)
+    ext = np.array([10.0 * (s - 1) for s in shape])
+    rng = np.random.default_rng(3)
+    pts = rng.uniform(0, 1, size=(6, 3)) * ext
+    pts = np.concatenate([pts, np.repeat([[201.3, 170.7, 140.1]], 3, axis=0)])
+    prob = W.small_problem(kind, shape, 8, nt=25, seed=9, src_at=pts, nrec=10)
+    say("many sources", kind, prob.src.shape)
+    gf, gtr, desc = gpu_run(prob, torch_dev)
+    assert "src=kernel" in desc
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_points_on_edges_and_corners(torch_dev, ndim):
+    shape = (31, 26, 22)[:ndim]
+    ext = [10.0 * (s - 1) for s in shape]
+    corners = [list(ext), [0.0] * ndim, [ext[0], *([0.0] * (ndim - 1))], [0.0, *ext[1:]]]
+    src = [list(ext), [0.0] * ndim]  # last node (clamped base) and origin
+    prob = W.small_problem("iso", shape, 8, nt=30, seed=4, src_at=src, rec_coords=corners + [[e / 2 for e in ext]],
+                           nbl=3)
+    say("edges", ndim)
+    gf, gtr, _ = gpu_run(prob, torch_dev)
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+
+
+def test_nonzero_initial_levels(torch_dev):
+    prob = W.small_problem("tti", (29, 23, 19), 8, nt=20, seed=12, nrec=8)
+    rng = np.random.default_rng(5)
+    ash = prob.array_shape
+    init = {"p": (rng.standard_normal(ash).astype(np.float32).astype(np.float64),
+                  rng.standard_normal(ash).astype(np.float32).astype(np.float64)),
+            "r": (rng.standard_normal(ash).astype(np.float32).astype(np.float64),
+                  rng.standard_normal(ash).astype(np.float32).astype(np.float64))}
+    say("nonzero initial levels")
+    gf, gtr, _ = gpu_run(prob, torch_dev, u_init=init)
+    of, otr = oracle_run(prob, u_init=init)
+    check(prob, gf, gtr, of, otr)
+
+
+@pytest.mark.parametrize("kind", ["iso", "tti"])
+def test_split_apply_is_identical(torch_dev, kind):
+    prob = W.small_problem(kind, (35, 30, 26), 8, nt=24, seed=21, nrec=9)
+    say("split apply", kind)
+    f1, t1, _ = gpu_run(prob, torch_dev)
+    f2, t2, _ = gpu_run(prob, torch_dev, splits=[0, 7, 15])
+    f3, t3, _ = gpu_run(prob, torch_dev, time_M=-1)
+    for nm in f1:
+        np.testing.assert_array_equal(f1[nm][1], f2[nm][1])
+        np.testing.assert_array_equal(f1[nm][0], f2[nm][0])
+        np.testing.assert_array_equal(f1[nm][1], f3[nm][1])
+    np.testing.assert_array_equal(t1, t2)
+    np.testing.assert_array_equal(t1, t3)
+
+
+def test_no_sparse_points(torch_dev):
+    prob = W.small_problem("iso", (21, 19, 17), 4, nt=10, seed=2, src_at=np.zeros((0, 3)),
+                           rec_coords=np.zeros((0, 3)))
+    rng = np.random.default_rng(1)
+    init = {"u": (np.zeros(prob.array_shape), rng.standard_normal(prob.array_shape).astype(np.float32).astype(float))}
+    say("no sparse points")
+    gf, gtr, _ = gpu_run(prob, torch_dev, u_init=init)
+    of, otr = oracle_run(prob, u_init=init)
+    check(prob, gf, gtr, of, otr)
+
+
+# ---------------------------------------------------------- full-size configs
+def test_config_2d_iso_101_full(torch_dev):
+    """101 x 101, so = 4, 500 steps: full oracle run, every output compared."""
+    prob = W.config_2d_iso_101()
+    say(prob.name)
+    gf, gtr, _ = gpu_run(prob, torch_dev)
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+
+
+def test_config_3d_iso_256_short_full_grid(torch_dev):
+    """256^3, so = 8, first 40 steps on the full grid: every output compared."""
+    prob = W.config_3d_iso_256(nt=40)
+    say(prob.name, "nt=40")
+    gf, gtr, _ = gpu_run(prob, torch_dev)
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+
+
+def _sampled_check(name, prob, gf, gtr):
+    path = os.path.join(GOLDEN, f"full_{name}.npz")
+    z = np.load(path)
+    meta = json.loads(str(z["meta"]))
+    assert meta["nt"] == prob.nt
+    errs = {}
+    for nm in gf:
+        for tag, lv in (("prev", 0), ("cur", 1)):
+            idx = z[f"{nm}_{tag}_idx"]
+            ref = z[f"{nm}_{tag}_val"]
+            got = gf[nm][lv].reshape(-1)[idx]
+            errs[f"{nm}_{tag}"] = rel_l2(got, ref)
+    errs["rec"] = rel_l2(gtr[:, z["rec_idx"]], z["rec_val"])
+    say(name, "sampled", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= TOL, (name, k, v)
+    assert np.all(np.isfinite(gtr))
+
+
+def test_config_3d_iso_256_full_sampled(torch_dev):
+    """256^3, so = 8, all 1000 steps: sampled outputs against stored oracle values."""
+    if not os.path.exists(os.path.join(GOLDEN, "full_3d_iso_256.npz")):
+        pytest.skip("stored oracle samples not generated")
+    prob = W.config_3d_iso_256()
+    say(prob.name, "full")
+    gf, gtr, _ = gpu_run(prob, torch_dev)
+    _sampled_check("3d_iso_256", prob, gf, gtr)
+
+
+def test_config_3d_tti_512_full_sampled(torch_dev):
+    """512^3, so = 12, all 800 steps: sampled outputs against stored oracle values."""
+    if not os.path.exists(os.path.join(GOLDEN, "full_3d_tti_512.npz")):
+        pytest.skip("stored oracle samples not generated")
+    prob = W.config_3d_tti_512()
+    say(prob.name, "full")
+    gf, gtr, _ = gpu_run(prob, torch_dev)
+    _sampled_check("3d_tti_512", prob, gf, gtr)
