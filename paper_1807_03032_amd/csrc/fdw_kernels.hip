@@ -173,46 +173,70 @@ __global__ void __launch_bounds__(256) tti_naive_stage2(TtiArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// 3D isotropic z-streaming kernel (2.5D blocking).
+// 3D z-streaming engine (2.5D blocking), shared by the isotropic step and the
+// two TTI stages.
 //
-// A workgroup of 4 wavefronts owns a 64 x TY tile of (x, y) columns
-// (TY = 4 * NY: each thread owns NY consecutive y columns at one x) and marches
-// along z over a chunk [z0, z0 + zc).  For every plane:
-//   * the u(t) values of the z-stencil live in a per-thread register queue of
-//     2R + 1 planes, so each u(t) element of the tile is loaded from memory
-//     once per chunk (plus 2R warm-up planes);
-//   * the x/y neighbours come from an LDS copy of the plane with an R-wide
-//     x and y halo (no corners), double buffered so one barrier per plane
-//     suffices;
-//   * loads for plane z + 1 (queue head, u(t-1), m, halo) are issued before
-//     the plane-z arithmetic so their latency overlaps it.
-// Points outside the domain are never read: the zero Dirichlet halo is
-// written into LDS / the queue directly.  Workgroup ids are remapped so that
-// the workgroups one XCD receives (ids congruent mod 8) form a contiguous
-// block of tiles and share halo rows and warm-up planes in that XCD's L2.
+// A workgroup of BY wavefronts owns a 64 x TY tile of (x, y) columns
+// (TY = BY * NY: each thread owns NY consecutive y columns at one x) and marches
+// along z over a chunk [z0, z0 + zc).  Two kinds of input fields:
+//   * NQ "stencil" fields, read at z - R .. z + R: each thread keeps a
+//     register queue of 2R + 1 planes per column (z neighbours), and the
+//     workgroup keeps the current plane with an R-wide x/y halo (no corners) in
+//     LDS (x/y neighbours), double buffered so one barrier per plane suffices;
+//   * NP "pointwise" fields, read only at the output point.
+// Loads for plane z + PF (queue heads, pointwise values, halo) are issued
+// before the plane-z arithmetic, so PF planes of loads are in flight.
+// Points outside the domain are never read: the zero Dirichlet halo is written
+// into LDS / the queues directly.  Workgroup ids are remapped so that the
+// workgroups one XCD receives (ids congruent mod 8) cover a contiguous block of
+// tiles and share halo rows and warm-up planes in that XCD's L2.
+// The operator functor Op computes and stores the outputs of one point from
+// a StreamPoint view of the registers and LDS.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int xcd_tile(int bid, int nb) {
     const int q = nb / 8, r = nb % 8, k = bid % 8;
     return k * q + (k < r ? k : r) + bid / 8;
 }
 
-// Loads of one plane that a thread issues ahead of use (prefetch ring entry).
-template <int NY, int NHY, int NHX>
-struct IsoPlaneLoads {
-    float head[NY];  // u(t) at z + R (queue head)
-    float prev[NY];  // u(t-1) at z
-    float m[NY];     // m at z
-    float hy[NHY];   // y-halo rows of u(t) at z
-    float hx[NHX];   // x-halo elements of u(t) at z
+template <int NQ, int NP>
+struct StreamFields {
+    const float *q[NQ];  // stencil fields
+    const float *p[NP];  // pointwise fields
+    float pout[NP];      // value used outside the domain
 };
 
-template <int R, int NY, int PF>
-__global__ void __launch_bounds__(256) iso3d_stream(IsoArgs a, int zc, int ntx, int nty) {
-    constexpr int TX = 64, BY = 4, TY = BY * NY, LW = TX + 2 * R, LH = TY + 2 * R, Q = 2 * R + 1;
-    constexpr int NHY = (2 * R + BY - 1) / BY;     // y-halo rows per wavefront
-    constexpr int NHX = (TY * 2 * R + 255) / 256;  // x-halo elements per thread
-    __shared__ float lds[2][LH][LW];
-    const Geom &g = a.g;
+// Loads of one plane that a thread issues ahead of use (prefetch ring entry).
+template <int NQ, int NP, int NY, int NHY, int NHX>
+struct PlaneLoads {
+    float head[NQ][NY];  // stencil fields at z + R (queue heads)
+    float pw[NP][NY];    // pointwise fields at z
+    float hy[NQ][NHY];   // y-halo rows at z
+    float hx[NQ][NHX];   // x-halo elements at z
+};
+
+// What an operator sees for one output point.
+template <int R, int NQ, int NP, int NY, int LH, int LW>
+struct StreamPoint {
+    const float (&q)[NQ][NY][2 * R + 1];
+    const float (&lds)[NQ][LH][LW];
+    const float (&pw)[NP][NY];
+    int j, ly, lx;        // column index in the thread, LDS coordinates
+    int x, y, z;          // grid coordinates
+    uint32_t off;         // element offset of the point
+    // field f at (x, y, z + k), (x + k, y, z), (x, y + k, z); k in [-R, R]
+    __device__ __forceinline__ float qz(int f, int k) const { return q[f][j][R + k]; }
+    __device__ __forceinline__ float qx(int f, int k) const { return lds[f][ly][lx + k]; }
+    __device__ __forceinline__ float qy(int f, int k) const { return lds[f][ly + k][lx]; }
+    __device__ __forceinline__ float p(int i) const { return pw[i][j]; }
+};
+
+template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
+__global__ void __launch_bounds__(64 * BY) stream3d(Op op, StreamFields<NQ, NP> F, Geom g, int zc, int ntx, int nty) {
+    constexpr int NT = 64 * BY;  // threads per workgroup
+    constexpr int TX = 64, TY = BY * NY, LW = TX + 2 * R, LH = TY + 2 * R, Q = 2 * R + 1;
+    constexpr int NHY = (2 * R + BY - 1) / BY;       // y-halo rows per wavefront
+    constexpr int NHX = (TY * 2 * R + NT - 1) / NT;  // x-halo elements per thread
+    __shared__ float lds[2][NQ][LH][LW];
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
     int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % ntx;
@@ -223,34 +247,29 @@ __global__ void __launch_bounds__(256) iso3d_stream(IsoArgs a, int zc, int ntx, 
     const int z1 = min(z0 + zc, g.nz);
     const int x = x0 + lane;
     const bool xin = x < g.nx;
-    const float *__restrict__ u = a.u_cur;
-    const float *__restrict__ up = a.u_prev;
-    const float *__restrict__ mm = a.m;
-    float *__restrict__ un = a.u_next;
     // 32-bit element offsets (a slot holds fewer than 2^31 elements)
     const uint32_t sy = (uint32_t)g.sy, sz = (uint32_t)g.sz;
-
     const int yb = y0 + wy * NY;  // first y column of this thread
     bool in[NY];
-    float ay[NY];
 #pragma unroll
-    for (int j = 0; j < NY; ++j) {
-        in[j] = xin && yb + j < g.ny;
-        ay[j] = in[j] ? a.eta_y[yb + j] : 0.0f;
-    }
+    for (int j = 0; j < NY; ++j) in[j] = xin && yb + j < g.ny;
     const uint32_t col0 = (uint32_t)(g.off0 + (int64_t)yb * g.sy + x);
-    const float ax = xin ? a.eta_x[x] : 0.0f;
+    // per-column constants of the operator, computed once
+    float colv[NY];
+#pragma unroll
+    for (int j = 0; j < NY; ++j) colv[j] = in[j] ? op.begin_column(x, yb + j) : 0.0f;
 
     // y-halo rows handled by this wavefront: hr = wy + BY * i
-    bool hy_in[NHY];
+    bool hy_in[NHY], hy_act[NHY];
     int hy_lds[NHY];
     uint32_t hy_col[NHY];
 #pragma unroll
     for (int i = 0; i < NHY; ++i) {
         const int hr = wy + BY * i;
         const int yy = hr < R ? y0 - R + hr : y0 + TY + (hr - R);
+        hy_act[i] = hr < 2 * R;
         hy_lds[i] = hr < R ? hr : R + TY + (hr - R);
-        hy_in[i] = hr < 2 * R && xin && yy >= 0 && yy < g.ny;
+        hy_in[i] = hy_act[i] && xin && yy >= 0 && yy < g.ny;
         hy_col[i] = hy_in[i] ? (uint32_t)(g.off0 + (int64_t)yy * g.sy + x) : 0u;
     }
     // x-halo elements handled by this thread (TY rows x 2R columns)
@@ -259,7 +278,7 @@ __global__ void __launch_bounds__(256) iso3d_stream(IsoArgs a, int zc, int ntx, 
     uint32_t hx_off[NHX];
 #pragma unroll
     for (int i = 0; i < NHX; ++i) {
-        const int xi = threadIdx.x + 256 * i;
+        const int xi = threadIdx.x + NT * i;
         hx_act[i] = xi < TY * 2 * R;
         const int hx_r = xi / (2 * R), hx_c = xi % (2 * R);
         const int hx_x = hx_c < R ? x0 - R + hx_c : x0 + TX + (hx_c - R);
@@ -268,110 +287,242 @@ __global__ void __launch_bounds__(256) iso3d_stream(IsoArgs a, int zc, int ntx, 
         hx_lcol[i] = hx_c < R ? hx_c : R + TX + (hx_c - R);
         hx_off[i] = hx_in[i] ? (uint32_t)(g.off0 + (int64_t)(y0 + hx_r) * g.sy + hx_x) : 0u;
     }
-
-    // does a fused source touch this workgroup's tile and chunk?
-    bool src_here = false;
-    for (int s = 0; s < a.src.n; ++s)
-        src_here |= a.src.bx[s] + 1 >= x0 && a.src.bx[s] <= x0 + TX - 1 && a.src.by[s] + 1 >= y0 &&
-                    a.src.by[s] <= y0 + TY - 1 && a.src.bz[s] + 1 >= z0 && a.src.bz[s] <= z1 - 1;
+    const bool tile_flag = op.begin_tile(x0, TX, y0, TY, z0, z1);
 
     auto zin = [&](int z) { return z >= 0 && z < g.nz; };
-    auto issue = [&](IsoPlaneLoads<NY, NHY, NHX> &P, int z) {
+    auto issue = [&](PlaneLoads<NQ, NP, NY, NHY, NHX> &P, int z) {
         const uint32_t zo = (uint32_t)z * sz;
         const uint32_t zh = (uint32_t)(z + R) * sz;
         const bool hin = zin(z + R);
 #pragma unroll
-        for (int j = 0; j < NY; ++j) {
-            P.head[j] = (in[j] && hin) ? u[col0 + j * sy + zh] : 0.0f;
-            P.prev[j] = in[j] ? up[col0 + j * sy + zo] : 0.0f;
-            P.m[j] = in[j] ? mm[col0 + j * sy + zo] : 1.0f;
+        for (int f = 0; f < NQ; ++f) {
+#pragma unroll
+            for (int j = 0; j < NY; ++j) P.head[f][j] = (in[j] && hin) ? F.q[f][col0 + j * sy + zh] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < NHY; ++i) P.hy[f][i] = hy_in[i] ? F.q[f][hy_col[i] + zo] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < NHX; ++i) P.hx[f][i] = hx_in[i] ? F.q[f][hx_off[i] + zo] : 0.0f;
         }
 #pragma unroll
-        for (int i = 0; i < NHY; ++i) P.hy[i] = hy_in[i] ? u[hy_col[i] + zo] : 0.0f;
+        for (int f = 0; f < NP; ++f)
 #pragma unroll
-        for (int i = 0; i < NHX; ++i) P.hx[i] = hx_in[i] ? u[hx_off[i] + zo] : 0.0f;
+            for (int j = 0; j < NY; ++j) P.pw[f][j] = in[j] ? F.p[f][col0 + j * sy + zo] : F.pout[f];
     };
 
-    // warm-up: queue holds u(z0 - R .. z0 + R - 1)
-    float q[NY][Q];
+    // warm-up: queues hold z0 - R .. z0 + R - 1
+    float q[NQ][NY][Q];
 #pragma unroll
-    for (int j = 0; j < NY; ++j)
+    for (int f = 0; f < NQ; ++f)
 #pragma unroll
-        for (int k = 0; k < 2 * R; ++k) {
-            const int z = z0 - R + k;
-            q[j][k] = (in[j] && zin(z)) ? u[col0 + j * sy + (uint32_t)z * sz] : 0.0f;
-        }
-    IsoPlaneLoads<NY, NHY, NHX> P[PF];
+        for (int j = 0; j < NY; ++j)
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k) {
+                const int z = z0 - R + k;
+                q[f][j][k] = (in[j] && zin(z)) ? F.q[f][col0 + j * sy + (uint32_t)z * sz] : 0.0f;
+            }
+    PlaneLoads<NQ, NP, NY, NHY, NHX> P[PF];
 #pragma unroll
     for (int s = 0; s < PF; ++s)
         if (z0 + s < z1) issue(P[s], z0 + s);
 
-    const float two = 2.0f;
     int buf = 0;
     for (int zb = z0; zb < z1; zb += PF) {
 #pragma unroll
         for (int s = 0; s < PF; ++s) {
             const int z = zb + s;
             if (z >= z1) break;
-            float cp[NY], cm[NY], chy[NHY], chx[NHX];
+            float cpw[NP][NY], chy[NQ][NHY], chx[NQ][NHX];
 #pragma unroll
-            for (int i = 0; i < NHX; ++i) chx[i] = P[s].hx[i];
+            for (int f = 0; f < NQ; ++f) {
 #pragma unroll
-            for (int j = 0; j < NY; ++j) {
-                q[j][2 * R] = P[s].head[j];
-                cp[j] = P[s].prev[j];
-                cm[j] = P[s].m[j];
+                for (int j = 0; j < NY; ++j) q[f][j][2 * R] = P[s].head[f][j];
+#pragma unroll
+                for (int i = 0; i < NHY; ++i) chy[f][i] = P[s].hy[f][i];
+#pragma unroll
+                for (int i = 0; i < NHX; ++i) chx[f][i] = P[s].hx[f][i];
             }
 #pragma unroll
-            for (int i = 0; i < NHY; ++i) chy[i] = P[s].hy[i];
+            for (int f = 0; f < NP; ++f)
+#pragma unroll
+                for (int j = 0; j < NY; ++j) cpw[f][j] = P[s].pw[f][j];
             if (z + PF < z1) issue(P[s], z + PF);
             // plane z into LDS
 #pragma unroll
-            for (int j = 0; j < NY; ++j) lds[buf][R + wy * NY + j][R + lane] = q[j][R];
+            for (int f = 0; f < NQ; ++f) {
 #pragma unroll
-            for (int i = 0; i < NHY; ++i)
-                if (wy + BY * i < 2 * R) lds[buf][hy_lds[i]][R + lane] = chy[i];
+                for (int j = 0; j < NY; ++j) lds[buf][f][R + wy * NY + j][R + lane] = q[f][j][R];
 #pragma unroll
-            for (int i = 0; i < NHX; ++i)
-                if (hx_act[i]) lds[buf][hx_lrow[i]][hx_lcol[i]] = chx[i];
+                for (int i = 0; i < NHY; ++i)
+                    if (hy_act[i]) lds[buf][f][hy_lds[i]][R + lane] = chy[f][i];
+#pragma unroll
+                for (int i = 0; i < NHX; ++i)
+                    if (hx_act[i]) lds[buf][f][hx_lrow[i]][hx_lcol[i]] = chx[f][i];
+            }
             __syncthreads();
-            const float az = a.eta_z[z];
+            const float plane_val = op.begin_plane(z);
 #pragma unroll
             for (int j = 0; j < NY; ++j) {
-                const int ly = R + wy * NY + j, lx = R + lane;
-                const float uc = q[j][R];
-                const float u2 = two * uc;
-                // Laplacian as sum_k w_k ((u+k + u-k) - 2u): no centre weight, so
-                // rounding the weights cannot add a spurious mass term
-                float lap = 0.0f;
-#pragma unroll
-                for (int k = 1; k <= R; ++k) {
-                    lap += a.c.w2[2][k] * ((q[j][R + k] + q[j][R - k]) - u2);
-                    lap += a.c.w2[0][k] * ((lds[buf][ly][lx + k] + lds[buf][ly][lx - k]) - u2);
-                    lap += a.c.w2[1][k] * ((lds[buf][ly + k][lx] + lds[buf][ly - k][lx]) - u2);
-                }
-                const float rm = fast_rcp(cm[j]);
-                const float cl = a.dt2 * rm * lap;
-                const float d = uc - cp[j];
-                const float damp = ax + ay[j] + az;
-                float v;
-                if (damp == 0.0f) {
-                    v = uc + (d + cl);
-                } else {
-                    v = uc + ((1.0f - damp) * d + cl) / (1.0f + damp);
-                }
-                if (src_here) v = fused_inject(a.src, 3, x, yb + j, z, rm, v);
-                if (in[j]) un[col0 + j * sy + (uint32_t)z * sz] = v;
+                StreamPoint<R, NQ, NP, NY, LH, LW> pt{q, lds[buf], cpw, j, R + wy * NY + j, R + lane,
+                                                      x, yb + j, z, col0 + j * sy + (uint32_t)z * sz};
+                // computed for every column (keeps the NY columns in one scheduling
+                // region); only stores are predicated on the column being in the domain
+                op.template point<R>(pt, tile_flag, colv[j] + plane_val, in[j]);
             }
-            // advance the queue
+            // advance the queues
 #pragma unroll
-            for (int j = 0; j < NY; ++j)
+            for (int f = 0; f < NQ; ++f)
 #pragma unroll
-                for (int k = 0; k < 2 * R; ++k) q[j][k] = q[j][k + 1];
+                for (int j = 0; j < NY; ++j)
+#pragma unroll
+                    for (int k = 0; k < 2 * R; ++k) q[f][j][k] = q[f][j][k + 1];
             buf ^= 1;
         }
     }
 }
+
+// Does any fused source's interpolation cell touch the box
+// [x0, x0 + tx) x [y0, y0 + ty) x [z0, z1)?
+__device__ __forceinline__ bool src_in_tile(const FusedSrc &src, int x0, int tx, int y0, int ty, int z0, int z1) {
+    bool hit = false;
+    for (int s = 0; s < src.n; ++s)
+        hit |= src.bx[s] + 1 >= x0 && src.bx[s] <= x0 + tx - 1 && src.by[s] + 1 >= y0 && src.by[s] <= y0 + ty - 1 &&
+               src.bz[s] + 1 >= z0 && src.bz[s] <= z1 - 1;
+    return hit;
+}
+
+// Damping factor a = eta dt / 2 at (x, y, z) from the per-axis tables.
+struct DampTables {
+    const float *ex, *ey, *ez;
+    __device__ __forceinline__ float at(int x, int y, int z) const { return ex[x] + ey[y] + ez[z]; }
+};
+
+// ---- isotropic step: stencil field u(t); pointwise u(t-1), m ----------------
+struct IsoOp {
+    Coefs c;
+    DampTables eta;
+    float dt2;
+    FusedSrc src;
+    float *u_next;
+    // does a fused source touch this tile and chunk?
+    __device__ __forceinline__ bool begin_tile(int x0, int tx, int y0, int ty, int z0, int z1) const {
+        return src_in_tile(src, x0, tx, y0, ty, z0, z1);
+    }
+    // damping: eta_x + eta_y per column, + eta_z per plane
+    __device__ __forceinline__ float begin_column(int x, int y) const { return eta.ex[x] + eta.ey[y]; }
+    __device__ __forceinline__ float begin_plane(int z) const { return eta.ez[z]; }
+    template <int R, class P>
+    __device__ __forceinline__ void point(const P &pt, bool src_here, float a, bool live) const {
+        const float uc = pt.qz(0, 0);
+        const float u2 = 2.0f * uc;
+        // Laplacian as sum_k w_k ((u+k + u-k) - 2u): no centre weight, so
+        // rounding the weights cannot add a spurious mass term
+        float lap = 0.0f;
+#pragma unroll
+        for (int k = 1; k <= R; ++k) {
+            lap += c.w2[2][k] * ((pt.qz(0, k) + pt.qz(0, -k)) - u2);
+            lap += c.w2[0][k] * ((pt.qx(0, k) + pt.qx(0, -k)) - u2);
+            lap += c.w2[1][k] * ((pt.qy(0, k) + pt.qy(0, -k)) - u2);
+        }
+        const float rm = fast_rcp(pt.p(1));
+        float v = leapfrog(uc, pt.p(0), dt2 * rm * lap, a);
+        if (src_here) v = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, v);
+        if (live) u_next[pt.off] = v;
+    }
+};
+
+// n = (sin th cos ph, sin th sin ph, cos th) with the hardware sin/cos
+// (arguments in [0, 2 pi) after range reduction by the builtin).
+__device__ __forceinline__ void tti_normal3(float th, float ph, float &nx, float &ny, float &nz) {
+    const float st = __sinf(th), ct = __cosf(th), sp = __sinf(ph), cp = __cosf(ph);
+    nx = st * cp;
+    ny = st * sp;
+    nz = ct;
+}
+
+// ---- TTI stage 1: stencil fields p, r; pointwise theta, phi ------------------
+//   gp = n . grad p,  gr = n . grad r   (order-2R centred first derivatives)
+struct TtiS1Op {
+    Coefs c;
+    float *gp, *gr;
+    __device__ __forceinline__ bool begin_tile(int, int, int, int, int, int) const { return false; }
+    __device__ __forceinline__ float begin_column(int, int) const { return 0.0f; }
+    __device__ __forceinline__ float begin_plane(int) const { return 0.0f; }
+    template <int R, class P>
+    __device__ __forceinline__ void point(const P &pt, bool, float, bool live) const {
+        float nx, ny, nz;
+        tti_normal3(pt.p(0), pt.p(1), nx, ny, nz);
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+#pragma unroll
+            for (int k = 1; k <= R; ++k) {
+                dx += c.w1[0][k] * (pt.qx(f, k) - pt.qx(f, -k));
+                dy += c.w1[1][k] * (pt.qy(f, k) - pt.qy(f, -k));
+                dz += c.w1[2][k] * (pt.qz(f, k) - pt.qz(f, -k));
+            }
+            const float gv = nx * dx + ny * dy + nz * dz;
+            if (live) (f == 0 ? gp : gr)[pt.off] = gv;
+        }
+    }
+};
+
+// ---- TTI stage 2: stencil fields gp, gr, p; pointwise p(t-1), r(t), r(t-1),
+// m, eps, delta, theta, phi --------------------------------------------------
+//   Hp = n . grad gp, Hr = n . grad gr, A = L p - Hp, B = Hr
+//   p+ from (1 + 2 eps) A + sqrt(1 + 2 delta) B, r+ from sqrt(1 + 2 delta) A + B
+struct TtiS2Op {
+    Coefs c;
+    DampTables eta;
+    float dt2;
+    FusedSrc src;
+    float *p_next, *r_next;
+    __device__ __forceinline__ bool begin_tile(int x0, int tx, int y0, int ty, int z0, int z1) const {
+        return src_in_tile(src, x0, tx, y0, ty, z0, z1);
+    }
+    __device__ __forceinline__ float begin_column(int x, int y) const { return eta.ex[x] + eta.ey[y]; }
+    __device__ __forceinline__ float begin_plane(int z) const { return eta.ez[z]; }
+    template <int R, class P>
+    __device__ __forceinline__ void point(const P &pt, bool src_here, float a, bool live) const {
+        float nx, ny, nz;
+        tti_normal3(pt.p(6), pt.p(7), nx, ny, nz);
+        float h[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+#pragma unroll
+            for (int k = 1; k <= R; ++k) {
+                dx += c.w1[0][k] * (pt.qx(f, k) - pt.qx(f, -k));
+                dy += c.w1[1][k] * (pt.qy(f, k) - pt.qy(f, -k));
+                dz += c.w1[2][k] * (pt.qz(f, k) - pt.qz(f, -k));
+            }
+            h[f] = nx * dx + ny * dy + nz * dz;
+        }
+        const float pc = pt.qz(2, 0);
+        const float p2 = 2.0f * pc;
+        float lap = 0.0f;
+#pragma unroll
+        for (int k = 1; k <= R; ++k) {
+            lap += c.w2[2][k] * ((pt.qz(2, k) + pt.qz(2, -k)) - p2);
+            lap += c.w2[0][k] * ((pt.qx(2, k) + pt.qx(2, -k)) - p2);
+            lap += c.w2[1][k] * ((pt.qy(2, k) + pt.qy(2, -k)) - p2);
+        }
+        const float A = lap - h[0];
+        const float B = h[1];
+        const float sd = __builtin_sqrtf(1.0f + 2.0f * pt.p(5));
+        const float rm = fast_rcp(pt.p(3));
+        const float cdt = dt2 * rm;
+        float pn = leapfrog(pc, pt.p(0), cdt * ((1.0f + 2.0f * pt.p(4)) * A + sd * B), a);
+        float rn = leapfrog(pt.p(1), pt.p(2), cdt * (sd * A + B), a);
+        if (src_here) {
+            pn = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, pn);
+            rn = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, rn);
+        }
+        if (live) {
+            p_next[pt.off] = pn;
+            r_next[pt.off] = rn;
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Sparse kernels.  One group of ncorner lanes per sparse point: lane c owns
@@ -467,41 +618,61 @@ static hipError_t launch_tti_naive(const TtiArgs &a, hipStream_t s) {
     default: return hipErrorInvalidValue; \
     }
 
-// Tile shape of the z-streaming kernel: NY y-columns per thread (tile 64 x 4NY),
-// z-chunk length ZC and prefetch distance PF (planes in flight);
-// FDW_ISO_TILE="NY,ZC[,PF]" overrides (tuning sweeps).
+template <int R, int NY, int PF, int BY, int NQ, int NP, class Op>
+static hipError_t launch_stream3d(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s) {
+    const int ntx = (g.nx + 63) / 64, nty = (g.ny + BY * NY - 1) / (BY * NY), ntz = (g.nz + zc - 1) / zc;
+    const int64_t nb = (int64_t)ntx * nty * ntz;
+    hipLaunchKernelGGL((stream3d<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)nb), dim3(64 * BY), 0, s, op, F, g, zc,
+                       ntx, nty);
+    return hipGetLastError();
+}
+
+// Tile shapes are (NY y-columns per thread, BY wavefronts per workgroup, z-chunk
+// ZC, prefetch PF); tile = 64 x (NY * BY).  Environment overrides for tuning:
+//   FDW_ISO_TILE="NY,ZC,PF,BY"   FDW_TTI_TILE="NY1,BY1,NY2,BY2,ZC"
 struct IsoShape {
-    int ny, zc, pf;
+    int ny, zc, pf, by;
 };
 
 static IsoShape iso_stream_shape(const Geom &g) {
-    IsoShape sh{4, 16, 2};
+    IsoShape sh{4, 16, 1, 4};
     if (const char *e = std::getenv("FDW_ISO_TILE")) {
-        int a = 0, b = 0, c = 2;
-        const int n = std::sscanf(e, "%d,%d,%d", &a, &b, &c);
-        if (n >= 2 && (a == 1 || a == 2 || a == 4 || a == 8) && b > 0 && (c == 1 || c == 2 || c == 3)) {
-            sh.ny = a;
-            sh.zc = b;
-            sh.pf = c;
-        }
+        int a = 0, b = 0, c = 1, d = 4;
+        const int n = std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d);
+        if (n >= 2 && (a == 1 || a == 2 || a == 4) && b > 0 && (c == 1 || c == 2) && (d == 4 || d == 8))
+            sh = IsoShape{a, b, c, d};
     }
     if (sh.zc > g.nz) sh.zc = g.nz;
     return sh;
 }
 
-template <int R, int NY, int PF>
+template <int R, int NY, int PF, int BY>
 static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t s) {
-    const int ntx = (a.g.nx + 63) / 64, nty = (a.g.ny + 4 * NY - 1) / (4 * NY), ntz = (a.g.nz + zc - 1) / zc;
-    const int64_t nb = (int64_t)ntx * nty * ntz;
-    hipLaunchKernelGGL((iso3d_stream<R, NY, PF>), dim3((unsigned)nb), dim3(256), 0, s, a, zc, ntx, nty);
-    return hipGetLastError();
+    IsoOp op;
+    op.c = a.c;
+    op.eta = DampTables{a.eta_x, a.eta_y, a.eta_z};
+    op.dt2 = a.dt2;
+    op.src = a.src;
+    op.u_next = a.u_next;
+    StreamFields<1, 2> F;
+    F.q[0] = a.u_cur;
+    F.p[0] = a.u_prev;
+    F.p[1] = a.m;
+    F.pout[0] = 0.0f;
+    F.pout[1] = 1.0f;
+    return launch_stream3d<R, NY, PF, BY>(op, F, a.g, zc, s);
+}
+
+template <int R, int NY, int PF>
+static hipError_t launch_iso3d_stream_by(const IsoArgs &a, const IsoShape &sh, hipStream_t s) {
+    if (sh.by == 8) return launch_iso3d_stream_cfg<R, NY, PF, 8>(a, sh.zc, s);
+    return launch_iso3d_stream_cfg<R, NY, PF, 4>(a, sh.zc, s);
 }
 
 template <int R, int NY>
 static hipError_t launch_iso3d_stream_ny(const IsoArgs &a, const IsoShape &sh, hipStream_t s) {
-    if (sh.pf == 1) return launch_iso3d_stream_cfg<R, NY, 1>(a, sh.zc, s);
-    if (sh.pf == 3) return launch_iso3d_stream_cfg<R, NY, 3>(a, sh.zc, s);
-    return launch_iso3d_stream_cfg<R, NY, 2>(a, sh.zc, s);
+    if (sh.pf == 2) return launch_iso3d_stream_by<R, NY, 2>(a, sh, s);
+    return launch_iso3d_stream_by<R, NY, 1>(a, sh, s);
 }
 
 template <int R>
@@ -509,8 +680,70 @@ static hipError_t launch_iso3d_stream(const IsoArgs &a, hipStream_t s) {
     const IsoShape sh = iso_stream_shape(a.g);
     if (sh.ny == 1) return launch_iso3d_stream_ny<R, 1>(a, sh, s);
     if (sh.ny == 2) return launch_iso3d_stream_ny<R, 2>(a, sh, s);
-    if (sh.ny == 8) return launch_iso3d_stream_ny<R, 8>(a, sh, s);
     return launch_iso3d_stream_ny<R, 4>(a, sh, s);
+}
+
+struct TtiShape {
+    int ny1, by1, ny2, by2, zc;
+};
+
+static TtiShape tti_stream_shape(const Geom &g) {
+    TtiShape sh{2, 8, 1, 8, 32};
+    if (const char *e = std::getenv("FDW_TTI_TILE")) {
+        int a = 0, b = 0, c = 0, d = 0, z = 0;
+        if (std::sscanf(e, "%d,%d,%d,%d,%d", &a, &b, &c, &d, &z) == 5 && (a == 1 || a == 2) && (b == 4 || b == 8) &&
+            (c == 1 || c == 2) && (d == 4 || d == 8) && z > 0)
+            sh = TtiShape{a, b, c, d, z};
+    }
+    if (sh.zc > g.nz) sh.zc = g.nz;
+    return sh;
+}
+
+template <int R, int NY, int BY, class Op, int NQ, int NP>
+static hipError_t launch_tti_stage(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s) {
+    return launch_stream3d<R, NY, 1, BY>(op, F, g, zc, s);
+}
+
+template <int R, class Op, int NQ, int NP>
+static hipError_t launch_tti_stage_shape(int ny, int by, const Op &op, const StreamFields<NQ, NP> &F, const Geom &g,
+                                         int zc, hipStream_t s) {
+    if (ny == 2) return by == 8 ? launch_tti_stage<R, 2, 8>(op, F, g, zc, s) : launch_tti_stage<R, 2, 4>(op, F, g, zc, s);
+    return by == 8 ? launch_tti_stage<R, 1, 8>(op, F, g, zc, s) : launch_tti_stage<R, 1, 4>(op, F, g, zc, s);
+}
+
+template <int R>
+static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s) {
+    const TtiShape sh = tti_stream_shape(a.g);
+    TtiS1Op o1;
+    o1.c = a.c;
+    o1.gp = a.gp;
+    o1.gr = a.gr;
+    StreamFields<2, 2> F1;
+    F1.q[0] = a.p_cur;
+    F1.q[1] = a.r_cur;
+    F1.p[0] = a.theta;
+    F1.p[1] = a.phi;
+    F1.pout[0] = F1.pout[1] = 0.0f;
+    hipError_t e = launch_tti_stage_shape<R>(sh.ny1, sh.by1, o1, F1, a.g, sh.zc, s);
+    if (e != hipSuccess) return e;
+    TtiS2Op o2;
+    o2.c = a.c;
+    o2.eta = DampTables{a.eta_x, a.eta_y, a.eta_z};
+    o2.dt2 = a.dt2;
+    o2.src = a.src;
+    o2.p_next = a.p_next;
+    o2.r_next = a.r_next;
+    StreamFields<3, 8> F2;
+    F2.q[0] = a.gp;
+    F2.q[1] = a.gr;
+    F2.q[2] = a.p_cur;
+    const float *pw[8] = {a.p_prev, a.r_cur, a.r_prev, a.m, a.eps, a.delta, a.theta, a.phi};
+    for (int i = 0; i < 8; ++i) {
+        F2.p[i] = pw[i];
+        F2.pout[i] = 0.0f;
+    }
+    F2.pout[3] = 1.0f;  // m
+    return launch_tti_stage_shape<R>(sh.ny2, sh.by2, o2, F2, a.g, sh.zc, s);
 }
 
 hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream_t s) {
@@ -526,7 +759,9 @@ hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream
 }
 
 hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s) {
-    (void)v;
+#define TTI_S3(r) launch_tti3d_stream<r>(a, s)
+    if (ndim == 3 && v == TtiVariant::Stream) { FDW_DISPATCH_R(R, TTI_S3) }
+#undef TTI_S3
 #define TTI_N3(r) launch_tti_naive<3, r>(a, s)
 #define TTI_N2(r) launch_tti_naive<2, r>(a, s)
     if (ndim == 3) { FDW_DISPATCH_R(R, TTI_N3) }
@@ -563,14 +798,23 @@ const char *iso_kernel_name(int ndim, IsoVariant v) {
         Geom g{};
         g.nz = 1 << 30;
         const IsoShape sh = iso_stream_shape(g);
-        std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x%d zchunk=%d prefetch=%d", 4 * sh.ny, sh.zc, sh.pf);
+        std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x%d (%d waves) zchunk=%d prefetch=%d", sh.by * sh.ny,
+                      sh.by, sh.zc, sh.pf);
         return buf;
     }
     return ndim == 3 ? "iso_naive<3>" : "iso_naive<2>";
 }
 
 const char *tti_kernel_name(int ndim, TtiVariant v) {
-    (void)v;
+    if (ndim == 3 && v == TtiVariant::Stream) {
+        static char buf[96];
+        Geom g{};
+        g.nz = 1 << 30;
+        const TtiShape sh = tti_stream_shape(g);
+        std::snprintf(buf, sizeof(buf), "tti3d_stream stage1 tile=64x%d stage2 tile=64x%d zchunk=%d", sh.by1 * sh.ny1,
+                      sh.by2 * sh.ny2, sh.zc);
+        return buf;
+    }
     return ndim == 3 ? "tti_naive_stage1+2<3>" : "tti_naive_stage1+2<2>";
 }
 
