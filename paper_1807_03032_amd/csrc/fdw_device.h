@@ -1,0 +1,320 @@
+// Device-side building blocks shared by the HIP kernels of the wave-equation
+// operators (arXiv 1807.03032; Section 7.2 test cases, Section 3.3 sparse
+// points): leapfrog update, Laplacian, fused source injection, and the 3D
+// z-streaming engine that the isotropic step and both TTI stages run on.
+//
+// Every kernel reads and writes fields in the padded x-fastest layout of
+// fdw.h; halos hold zeros (Dirichlet) and are never written.
+#pragma once
+#include "fdw_internal.h"
+
+#include <cstdio>
+#include <cstdlib>
+
+namespace fdw {
+
+// ---------------------------------------------------------------------------
+// Shared device helpers
+// ---------------------------------------------------------------------------
+
+// 1/m with the hardware reciprocal (1 ulp); m = 1/v^2 is a normal float.
+__device__ __forceinline__ float fast_rcp(float m) { return __builtin_amdgcn_rcpf(m); }
+
+// Leapfrog update with the damping term (centred first time derivative):
+//   u+ = [2u - (1 - a) u- + c L] / (1 + a),   a = eta dt / 2,  c = dt^2 / m.
+// In the undamped interior a = 0 and no division is needed.
+// Written as u + increment, with d = u - u-:
+//   u+ = u + [(1 - a) d + c L] / (1 + a),
+// which rounds once at the scale of u instead of twice.
+__device__ __forceinline__ float leapfrog(float u, float u_prev, float cl, float a) {
+    const float d = u - u_prev;
+    if (a == 0.0f) return u + (d + cl);
+    return u + ((1.0f - a) * d + cl) / (1.0f + a);
+}
+
+// Laplacian at element i as sum over axes and k of w_k ((u(+k) + u(-k)) - 2u).
+// Summing differences instead of a separate centre weight keeps L exactly
+// zero on constants after the weights are rounded to float.
+template <int NDIM, int R>
+__device__ __forceinline__ float laplacian_at(const float *u, int64_t i, const Geom &g, const Coefs &c) {
+    const float u2 = 2.0f * u[i];
+    float lap = 0.0f;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+        lap += c.w2[0][k] * ((u[i + k] + u[i - k]) - u2);
+        lap += c.w2[2][k] * ((u[i + k * g.sz] + u[i - k * g.sz]) - u2);
+        if (NDIM == 3) lap += c.w2[1][k] * ((u[i + k * g.sy] + u[i - k * g.sy]) - u2);
+    }
+    return lap;
+}
+
+// Fused injection for the point (x, y, z): adds dt^2 w_c q_s / m for every
+// fused source s whose interpolation cell has this point as corner c.
+__device__ __forceinline__ float fused_inject(const FusedSrc &src, int ndim, int x, int y, int z,
+                                              float rcp_m, float val) {
+    for (int s = 0; s < src.n; ++s) {
+        const unsigned dx = (unsigned)(x - src.bx[s]);
+        const unsigned dy = (unsigned)(y - src.by[s]);
+        const unsigned dz = (unsigned)(z - src.bz[s]);
+        if (dx <= 1u && dy <= 1u && dz <= 1u) {
+            const int c = ndim == 3 ? (int)(dx + 2u * dy + 4u * dz) : (int)(dx + 2u * dz);
+            val += src.w[s][c] * src.q[s] * rcp_m;
+        }
+    }
+    return val;
+}
+
+__device__ __forceinline__ float damp_at(const float *ex, const float *ey, const float *ez, int ndim,
+                                         int x, int y, int z) {
+    float a = ex[x] + ez[z];
+    if (ndim == 3) a += ey[y];
+    return a;
+}
+
+#define FDW_DISPATCH_R(R_, CALL) \
+    switch (R_) {                \
+    case 1: return CALL(1);      \
+    case 2: return CALL(2);      \
+    case 3: return CALL(3);      \
+    case 4: return CALL(4);      \
+    case 5: return CALL(5);      \
+    case 6: return CALL(6);      \
+    case 7: return CALL(7);      \
+    case 8: return CALL(8);      \
+    default: return hipErrorInvalidValue; \
+    }
+
+// ---------------------------------------------------------------------------
+// 3D z-streaming engine (2.5D blocking), shared by the isotropic step and the
+// two TTI stages.
+//
+// A workgroup of BY wavefronts owns a 64 x TY tile of (x, y) columns
+// (TY = BY * NY: each thread owns NY consecutive y columns at one x) and marches
+// along z over a chunk [z0, z0 + zc).  Two kinds of input fields:
+//   * NQ "stencil" fields, read at z - R .. z + R: each thread keeps a
+//     register queue of 2R + 1 planes per column (z neighbours), and the
+//     workgroup keeps the current plane with an R-wide x/y halo (no corners) in
+//     LDS (x/y neighbours), double buffered so one barrier per plane suffices;
+//   * NP "pointwise" fields, read only at the output point.
+// Loads for plane z + PF (queue heads, pointwise values, halo) are issued
+// before the plane-z arithmetic, so PF planes of loads are in flight.
+// Points outside the domain are never read: the zero Dirichlet halo is written
+// into LDS / the queues directly.  Workgroup ids are remapped so that the
+// workgroups one XCD receives (ids congruent mod 8) cover a contiguous block of
+// tiles and share halo rows and warm-up planes in that XCD's L2.
+// The operator functor Op computes and stores the outputs of one point from
+// a StreamPoint view of the registers and LDS.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+    const int q = nb / 8, r = nb % 8, k = bid % 8;
+    return k * q + (k < r ? k : r) + bid / 8;
+}
+
+template <int NQ, int NP>
+struct StreamFields {
+    const float *q[NQ];  // stencil fields
+    const float *p[NP];  // pointwise fields
+    float pout[NP];      // value used outside the domain
+};
+
+// Loads of one plane that a thread issues ahead of use (prefetch ring entry).
+template <int NQ, int NP, int NY, int NHY, int NHX>
+struct PlaneLoads {
+    float head[NQ][NY];  // stencil fields at z + R (queue heads)
+    float pw[NP][NY];    // pointwise fields at z
+    float hy[NQ][NHY];   // y-halo rows at z
+    float hx[NQ][NHX];   // x-halo elements at z
+};
+
+// What an operator sees for one output point.
+template <int R, int NQ, int NP, int NY, int LH, int LW>
+struct StreamPoint {
+    const float (&q)[NQ][NY][2 * R + 1];
+    const float (&lds)[NQ][LH][LW];
+    const float (&pw)[NP][NY];
+    int j, ly, lx;        // column index in the thread, LDS coordinates
+    int x, y, z;          // grid coordinates
+    uint32_t off;         // element offset of the point
+    // field f at (x, y, z + k), (x + k, y, z), (x, y + k, z); k in [-R, R]
+    __device__ __forceinline__ float qz(int f, int k) const { return q[f][j][R + k]; }
+    __device__ __forceinline__ float qx(int f, int k) const { return lds[f][ly][lx + k]; }
+    __device__ __forceinline__ float qy(int f, int k) const { return lds[f][ly + k][lx]; }
+    __device__ __forceinline__ float p(int i) const { return pw[i][j]; }
+};
+
+template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
+__global__ void __launch_bounds__(64 * BY) stream3d(Op op, StreamFields<NQ, NP> F, Geom g, int zc, int ntx, int nty) {
+    constexpr int NT = 64 * BY;  // threads per workgroup
+    constexpr int TX = 64, TY = BY * NY, LW = TX + 2 * R, LH = TY + 2 * R, Q = 2 * R + 1;
+    constexpr int NHY = (2 * R + BY - 1) / BY;       // y-halo rows per wavefront
+    constexpr int NHX = (TY * 2 * R + NT - 1) / NT;  // x-halo elements per thread
+    __shared__ float lds[2][NQ][LH][LW];
+    const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+    int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % ntx;
+    tile /= ntx;
+    const int ty = tile % nty;
+    const int tz = tile / nty;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * zc;
+    const int z1 = min(z0 + zc, g.nz);
+    const int x = x0 + lane;
+    const bool xin = x < g.nx;
+    // 32-bit element offsets (a slot holds fewer than 2^31 elements)
+    const uint32_t sy = (uint32_t)g.sy, sz = (uint32_t)g.sz;
+    const int yb = y0 + wy * NY;  // first y column of this thread
+    bool in[NY];
+#pragma unroll
+    for (int j = 0; j < NY; ++j) in[j] = xin && yb + j < g.ny;
+    const uint32_t col0 = (uint32_t)(g.off0 + (int64_t)yb * g.sy + x);
+    // per-column constants of the operator, computed once
+    float colv[NY];
+#pragma unroll
+    for (int j = 0; j < NY; ++j) colv[j] = in[j] ? op.begin_column(x, yb + j) : 0.0f;
+
+    // y-halo rows handled by this wavefront: hr = wy + BY * i
+    bool hy_in[NHY], hy_act[NHY];
+    int hy_lds[NHY];
+    uint32_t hy_col[NHY];
+#pragma unroll
+    for (int i = 0; i < NHY; ++i) {
+        const int hr = wy + BY * i;
+        const int yy = hr < R ? y0 - R + hr : y0 + TY + (hr - R);
+        hy_act[i] = hr < 2 * R;
+        hy_lds[i] = hr < R ? hr : R + TY + (hr - R);
+        hy_in[i] = hy_act[i] && xin && yy >= 0 && yy < g.ny;
+        hy_col[i] = hy_in[i] ? (uint32_t)(g.off0 + (int64_t)yy * g.sy + x) : 0u;
+    }
+    // x-halo elements handled by this thread (TY rows x 2R columns)
+    bool hx_act[NHX], hx_in[NHX];
+    int hx_lrow[NHX], hx_lcol[NHX];
+    uint32_t hx_off[NHX];
+#pragma unroll
+    for (int i = 0; i < NHX; ++i) {
+        const int xi = threadIdx.x + NT * i;
+        hx_act[i] = xi < TY * 2 * R;
+        const int hx_r = xi / (2 * R), hx_c = xi % (2 * R);
+        const int hx_x = hx_c < R ? x0 - R + hx_c : x0 + TX + (hx_c - R);
+        hx_in[i] = hx_act[i] && hx_x >= 0 && hx_x < g.nx && y0 + hx_r < g.ny;
+        hx_lrow[i] = R + hx_r;
+        hx_lcol[i] = hx_c < R ? hx_c : R + TX + (hx_c - R);
+        hx_off[i] = hx_in[i] ? (uint32_t)(g.off0 + (int64_t)(y0 + hx_r) * g.sy + hx_x) : 0u;
+    }
+    const bool tile_flag = op.begin_tile(x0, TX, y0, TY, z0, z1);
+
+    auto zin = [&](int z) { return z >= 0 && z < g.nz; };
+    auto issue = [&](PlaneLoads<NQ, NP, NY, NHY, NHX> &P, int z) {
+        const uint32_t zo = (uint32_t)z * sz;
+        const uint32_t zh = (uint32_t)(z + R) * sz;
+        const bool hin = zin(z + R);
+#pragma unroll
+        for (int f = 0; f < NQ; ++f) {
+#pragma unroll
+            for (int j = 0; j < NY; ++j) P.head[f][j] = (in[j] && hin) ? F.q[f][col0 + j * sy + zh] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < NHY; ++i) P.hy[f][i] = hy_in[i] ? F.q[f][hy_col[i] + zo] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < NHX; ++i) P.hx[f][i] = hx_in[i] ? F.q[f][hx_off[i] + zo] : 0.0f;
+        }
+#pragma unroll
+        for (int f = 0; f < NP; ++f)
+#pragma unroll
+            for (int j = 0; j < NY; ++j) P.pw[f][j] = in[j] ? F.p[f][col0 + j * sy + zo] : F.pout[f];
+    };
+
+    // warm-up: queues hold z0 - R .. z0 + R - 1
+    float q[NQ][NY][Q];
+#pragma unroll
+    for (int f = 0; f < NQ; ++f)
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k) {
+                const int z = z0 - R + k;
+                q[f][j][k] = (in[j] && zin(z)) ? F.q[f][col0 + j * sy + (uint32_t)z * sz] : 0.0f;
+            }
+    PlaneLoads<NQ, NP, NY, NHY, NHX> P[PF];
+#pragma unroll
+    for (int s = 0; s < PF; ++s)
+        if (z0 + s < z1) issue(P[s], z0 + s);
+
+    int buf = 0;
+    for (int zb = z0; zb < z1; zb += PF) {
+#pragma unroll
+        for (int s = 0; s < PF; ++s) {
+            const int z = zb + s;
+            if (z >= z1) break;
+            float cpw[NP][NY], chy[NQ][NHY], chx[NQ][NHX];
+#pragma unroll
+            for (int f = 0; f < NQ; ++f) {
+#pragma unroll
+                for (int j = 0; j < NY; ++j) q[f][j][2 * R] = P[s].head[f][j];
+#pragma unroll
+                for (int i = 0; i < NHY; ++i) chy[f][i] = P[s].hy[f][i];
+#pragma unroll
+                for (int i = 0; i < NHX; ++i) chx[f][i] = P[s].hx[f][i];
+            }
+#pragma unroll
+            for (int f = 0; f < NP; ++f)
+#pragma unroll
+                for (int j = 0; j < NY; ++j) cpw[f][j] = P[s].pw[f][j];
+            if (z + PF < z1) issue(P[s], z + PF);
+            // plane z into LDS
+#pragma unroll
+            for (int f = 0; f < NQ; ++f) {
+#pragma unroll
+                for (int j = 0; j < NY; ++j) lds[buf][f][R + wy * NY + j][R + lane] = q[f][j][R];
+#pragma unroll
+                for (int i = 0; i < NHY; ++i)
+                    if (hy_act[i]) lds[buf][f][hy_lds[i]][R + lane] = chy[f][i];
+#pragma unroll
+                for (int i = 0; i < NHX; ++i)
+                    if (hx_act[i]) lds[buf][f][hx_lrow[i]][hx_lcol[i]] = chx[f][i];
+            }
+            __syncthreads();
+            const float plane_val = op.begin_plane(z);
+#pragma unroll
+            for (int j = 0; j < NY; ++j) {
+                StreamPoint<R, NQ, NP, NY, LH, LW> pt{q, lds[buf], cpw, j, R + wy * NY + j, R + lane,
+                                                      x, yb + j, z, col0 + j * sy + (uint32_t)z * sz};
+                // computed for every column (keeps the NY columns in one scheduling
+                // region); only stores are predicated on the column being in the domain
+                op.template point<R>(pt, tile_flag, colv[j] + plane_val, in[j]);
+            }
+            // advance the queues
+#pragma unroll
+            for (int f = 0; f < NQ; ++f)
+#pragma unroll
+                for (int j = 0; j < NY; ++j)
+#pragma unroll
+                    for (int k = 0; k < 2 * R; ++k) q[f][j][k] = q[f][j][k + 1];
+            buf ^= 1;
+        }
+    }
+}
+
+// Does any fused source's interpolation cell touch the box
+// [x0, x0 + tx) x [y0, y0 + ty) x [z0, z1)?
+__device__ __forceinline__ bool src_in_tile(const FusedSrc &src, int x0, int tx, int y0, int ty, int z0, int z1) {
+    bool hit = false;
+    for (int s = 0; s < src.n; ++s)
+        hit |= src.bx[s] + 1 >= x0 && src.bx[s] <= x0 + tx - 1 && src.by[s] + 1 >= y0 && src.by[s] <= y0 + ty - 1 &&
+               src.bz[s] + 1 >= z0 && src.bz[s] <= z1 - 1;
+    return hit;
+}
+
+// Damping factor a = eta dt / 2 at (x, y, z) from the per-axis tables.
+struct DampTables {
+    const float *ex, *ey, *ez;
+    __device__ __forceinline__ float at(int x, int y, int z) const { return ex[x] + ey[y] + ez[z]; }
+};
+
+template <int R, int NY, int PF, int BY, int NQ, int NP, class Op>
+static hipError_t launch_stream3d(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s) {
+    const int ntx = (g.nx + 63) / 64, nty = (g.ny + BY * NY - 1) / (BY * NY), ntz = (g.nz + zc - 1) / zc;
+    const int64_t nb = (int64_t)ntx * nty * ntz;
+    hipLaunchKernelGGL((stream3d<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)nb), dim3(64 * BY), 0, s, op, F, g, zc,
+                       ntx, nty);
+    return hipGetLastError();
+}
+
+}  // namespace fdw

@@ -102,6 +102,7 @@ struct fdw_op {
     float dt2;
     IsoVariant iso_v = IsoVariant::Naive;
     TtiVariant tti_v = TtiVariant::Naive;
+    bool use_persist2d = false;  // 2D iso grid small enough for the LDS-resident kernel
     // library-owned device memory
     float *d_eta = nullptr;           // eta_x | eta_y | eta_z (times dt/2)
     float *d_stage = nullptr;         // TTI: gp | gr (each elems_per_slot)
@@ -439,6 +440,8 @@ static void pick_variants(fdw_op *op) {
     const bool naive = k && std::strcmp(k, "naive") == 0;
     op->iso_v = naive ? IsoVariant::Naive : IsoVariant::Stream;
     op->tti_v = naive ? TtiVariant::Naive : TtiVariant::Stream;
+    op->use_persist2d = !naive && op->d.kind == FDW_ISO && op->ndim == 2 &&
+                        (int64_t)op->geom.nx * op->geom.nz * (int64_t)sizeof(float) <= kPersist2DMaxLds;
 }
 
 extern "C" {
@@ -687,6 +690,44 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
     itp.w = op->d_rec_w;
     itp.m = nullptr;
 
+    // small 2D isotropic grids: the whole range in one persistent launch
+    if (d.kind == FDW_ISO && op->ndim == 2 && op->use_persist2d && time_M >= time_m) {
+        Persist2DArgs pa{};
+        pa.g = op->geom;
+        pa.u = d.u->d;
+        pa.slot = E;
+        pa.pitch_x = L.pitch_x;
+        pa.m = d.m->d;
+        pa.eta_x = eta_x;
+        pa.eta_z = eta_z;
+        pa.dt2 = op->dt2;
+        pa.c = op->coefs;
+        pa.time_m = time_m;
+        pa.time_M = time_M;
+        pa.nsrc = nsrc;
+        pa.src_base = op->d_src_base;
+        pa.src_w = op->d_src_w;
+        pa.src_data = nsrc > 0 ? d.src->data : nullptr;
+        pa.nrec = nrec;
+        pa.rec_base = op->d_rec_base;
+        pa.rec_w = op->d_rec_w;
+        pa.rec_data = nrec > 0 ? d.rec->data : nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (op->timing) {
+            int st = timing_event_pair(op, &e0, &e1);
+            if (st) return st;
+            hipError_t er = hipEventRecord(e0, s);
+            if (er != hipSuccess) return fail_hip(er, "operator_apply: hipEventRecord");
+        }
+        hipError_t e = launch_iso2d_persistent(op->R, pa, s);
+        if (e != hipSuccess) return fail_hip(e, "operator_apply: persistent 2D launch");
+        if (op->timing) {
+            hipError_t er = hipEventRecord(e1, s);
+            if (er != hipSuccess) return fail_hip(er, "operator_apply: hipEventRecord");
+            op->acc_launches++;
+        }
+        return FDW_OK;
+    }
     for (int t = time_m; t <= time_M; ++t) {
         const int sc = t % 3, sp = (t + 2) % 3, sn = (t + 1) % 3;
         FusedSrc fs{};
@@ -810,7 +851,9 @@ int fdw_operator_kernel_time(fdw_op *op, double *total_ms, int64_t *launches, in
 int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_bytes_per_point) {
     if (!op || !buf || buflen <= 0) return fail(FDW_ERR_ARG, "describe: NULL argument");
     const bool iso = op->d.kind == FDW_ISO;
-    const char *name = iso ? iso_kernel_name(op->ndim, op->iso_v) : tti_kernel_name(op->ndim, op->tti_v);
+    const char *name = iso ? (op->use_persist2d ? "iso2d_persistent (LDS-resident, one launch per apply)"
+                                                : iso_kernel_name(op->ndim, op->iso_v))
+                           : tti_kernel_name(op->ndim, op->tti_v);
     snprintf(buf, (size_t)buflen, "%s so=%d R=%d ndim=%d src=%s nsrc=%d nrec=%d", name, op->d.space_order, op->R,
              op->ndim, op->src_fused ? "fused" : "kernel", op->d.src ? op->d.src->npoint : 0,
              op->d.rec ? op->d.rec->npoint : 0);

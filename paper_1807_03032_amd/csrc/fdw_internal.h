@@ -76,6 +76,33 @@ struct SparseArgs {
     float *rec_row;              // interpolation: output row of this step
 };
 
+// Whole-run 2D isotropic kernel: one workgroup runs steps time_m..time_M of
+// a small 2D grid with the current level resident in LDS.
+struct Persist2DArgs {
+    Geom g;
+    float *u;            // TimeFunction base (3 slots)
+    int64_t slot;        // elements per slot
+    int64_t pitch_x;     // row pitch of the padded layout
+    const float *m;
+    const float *eta_x, *eta_z;
+    float dt2;
+    Coefs c;
+    int time_m, time_M;
+    // sources (any number): padded element offset of corner 0, dt^2 * weights
+    int nsrc;
+    const int64_t *src_base;
+    const float *src_w;
+    const float *src_data;  // [nt][nsrc]
+    // receivers
+    int nrec;
+    const int64_t *rec_base;
+    const float *rec_w;
+    float *rec_data;        // [nt][nrec]
+};
+
+// Largest LDS footprint (bytes) the persistent 2D kernel may use.
+constexpr int kPersist2DMaxLds = 152 * 1024;
+
 // Kernel variants selectable per operator (FDW_KERNEL environment knob).
 enum class IsoVariant { Naive = 0, Stream = 1 };
 enum class TtiVariant { Naive = 0, Stream = 1 };
@@ -85,6 +112,7 @@ hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream
 hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s);
 hipError_t launch_inject(const SparseArgs &a, hipStream_t s);
 hipError_t launch_interp(const SparseArgs &a, hipStream_t s);
+hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s);
 hipError_t launch_zero_halo(int ndim, const Geom &g, int R, int64_t pitch_x, int64_t pitch_y,
                             int64_t planes, float *base, hipStream_t s);
 

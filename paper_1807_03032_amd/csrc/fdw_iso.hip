@@ -1,0 +1,325 @@
+// Isotropic acoustic step kernels (gfx950): 3D z-streaming operator, the
+// one-thread-per-point schedule, and the LDS-resident persistent 2D kernel.
+// Paper: arXiv 1807.03032, eq. WE and Listings fd-2/fd-3 (update), Listing
+// finject (injection), Section 7.2 (damping layer, test cases).
+#include "fdw_device.h"
+
+namespace fdw {
+
+// ---------------------------------------------------------------------------
+// Naive kernels: one thread per grid point, every neighbour loaded from
+// global memory (cache-served).  Kept as the simplest correct schedule and as
+// the fallback for shapes the streaming kernels do not cover.
+// ---------------------------------------------------------------------------
+
+template <int NDIM, int R>
+__global__ void __launch_bounds__(256) iso_naive(IsoArgs a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
+    const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+    const int64_t i = a.g.off0 + (int64_t)z * a.g.sz + (int64_t)y * a.g.sy + x;
+    const float *u = a.u_cur;
+    const float uc = u[i];
+    const float lap = laplacian_at<NDIM, R>(u, i, a.g, a.c);
+    const float rm = fast_rcp(a.m[i]);
+    const float d = damp_at(a.eta_x, a.eta_y, a.eta_z, NDIM, x, y, z);
+    float un = leapfrog(uc, a.u_prev[i], a.dt2 * rm * lap, d);
+    if (a.src.n) un = fused_inject(a.src, NDIM, x, y, z, rm, un);
+    a.u_next[i] = un;
+}
+
+// ---- isotropic step: stencil field u(t); pointwise u(t-1), m ----------------
+struct IsoOp {
+    Coefs c;
+    DampTables eta;
+    float dt2;
+    FusedSrc src;
+    float *u_next;
+    // does a fused source touch this tile and chunk?
+    __device__ __forceinline__ bool begin_tile(int x0, int tx, int y0, int ty, int z0, int z1) const {
+        return src_in_tile(src, x0, tx, y0, ty, z0, z1);
+    }
+    // damping: eta_x + eta_y per column, + eta_z per plane
+    __device__ __forceinline__ float begin_column(int x, int y) const { return eta.ex[x] + eta.ey[y]; }
+    __device__ __forceinline__ float begin_plane(int z) const { return eta.ez[z]; }
+    template <int R, class P>
+    __device__ __forceinline__ void point(const P &pt, bool src_here, float a, bool live) const {
+        const float uc = pt.qz(0, 0);
+        const float u2 = 2.0f * uc;
+        // Laplacian as sum_k w_k ((u+k + u-k) - 2u): no centre weight, so
+        // rounding the weights cannot add a spurious mass term
+        float lap = 0.0f;
+#pragma unroll
+        for (int k = 1; k <= R; ++k) {
+            lap += c.w2[2][k] * ((pt.qz(0, k) + pt.qz(0, -k)) - u2);
+            lap += c.w2[0][k] * ((pt.qx(0, k) + pt.qx(0, -k)) - u2);
+            lap += c.w2[1][k] * ((pt.qy(0, k) + pt.qy(0, -k)) - u2);
+        }
+        const float rm = fast_rcp(pt.p(1));
+        float v = leapfrog(uc, pt.p(0), dt2 * rm * lap, a);
+        if (src_here) v = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, v);
+        if (live) u_next[pt.off] = v;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Persistent 2D isotropic kernel: one workgroup of 1024 threads runs every
+// step of the apply for a grid small enough that its current level fits in
+// LDS (nx * nz floats, no halo: neighbours outside the domain read as zero).
+// Each thread owns the points i = tid + 1024 p and keeps, in registers, their
+// previous level and (for small grids) dt^2/m and the damping factor.  Per
+// step:
+//   1. update the owned points from the LDS level (results in registers);
+//   2. barrier; the owned points' LDS values become their previous level,
+//      the results replace them in LDS;
+//   3. barrier; source corners are added in LDS with LDS atomics;
+//   4. barrier; receivers are interpolated from LDS (4 corners, one thread
+//      each) and, in the last three steps, the level is written to its slot.
+// After the apply the three slots hold the same levels as with per-step
+// launches (levels time_M - 1, time_M, time_M + 1 in their slots).
+// ---------------------------------------------------------------------------
+template <int R, int PPT, bool HALO>
+__global__ void __launch_bounds__(1024) iso2d_persistent(Persist2DArgs a) {
+    constexpr bool kCacheCoef = PPT <= 16;
+    // LDS level: (nz + 2R) x (nx + 2R) with a zero halo when HALO, else nz x nx
+    // with neighbours outside the domain read as zero
+    extern __shared__ float lds_level[];
+    const int nx = a.g.nx, nz = a.g.nz;
+    const int n = nx * nz;
+    const int lw = HALO ? nx + 2 * R : nx;
+    float *cur = HALO ? lds_level + R * lw + R : lds_level;  // cur[z * lw + x]
+    auto li = [&](int i) { return HALO ? (i / nx) * lw + (i % nx) : i; };
+    const int tid = threadIdx.x;
+    const int64_t off0 = a.g.off0, px = a.pitch_x;
+    auto goff = [&](int i) { return off0 + (int64_t)(i / nx) * px + (i % nx); };
+    float prev[PPT], cdt[kCacheCoef ? PPT : 1], damp[kCacheCoef ? PPT : 1];
+    {
+        const float *uc = a.u + (int64_t)(a.time_m % 3) * a.slot;
+        const float *up = a.u + (int64_t)((a.time_m + 2) % 3) * a.slot;
+        if (HALO)
+            for (int i = tid; i < (nz + 2 * R) * lw; i += 1024) lds_level[i] = 0.0f;
+        __syncthreads();
+        for (int i = tid; i < n; i += 1024) cur[li(i)] = uc[goff(i)];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int i = tid + 1024 * p;
+            prev[p] = i < n ? up[goff(i)] : 0.0f;
+            if constexpr (kCacheCoef) {
+                cdt[p] = i < n ? a.dt2 * fast_rcp(a.m[goff(i)]) : 0.0f;
+                damp[p] = i < n ? a.eta_x[i % nx] + a.eta_z[i / nx] : 0.0f;
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = a.time_m; t <= a.time_M; ++t) {
+        float v[PPT];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int i = tid + 1024 * p;
+            v[p] = 0.0f;
+            if (i < n) {
+                const int x = i % nx, z = i / nx;
+                const int l = z * lw + x;
+                const float uc = cur[l];
+                const float u2 = 2.0f * uc;
+                float lap = 0.0f;
+#pragma unroll
+                for (int k = 1; k <= R; ++k) {
+                    const float xp = (HALO || x + k < nx) ? cur[l + k] : 0.0f;
+                    const float xm = (HALO || x - k >= 0) ? cur[l - k] : 0.0f;
+                    const float zp = (HALO || z + k < nz) ? cur[l + k * lw] : 0.0f;
+                    const float zm = (HALO || z - k >= 0) ? cur[l - k * lw] : 0.0f;
+                    lap += a.c.w2[0][k] * ((xp + xm) - u2);
+                    lap += a.c.w2[2][k] * ((zp + zm) - u2);
+                }
+                float c, dmp;
+                if constexpr (kCacheCoef) {
+                    c = cdt[p];
+                    dmp = damp[p];
+                } else {
+                    c = a.dt2 * fast_rcp(a.m[goff(i)]);
+                    dmp = a.eta_x[x] + a.eta_z[z];
+                }
+                v[p] = leapfrog(uc, prev[p], c * lap, dmp);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int i = tid + 1024 * p;
+            if (i < n) {
+                prev[p] = cur[li(i)];
+                cur[li(i)] = v[p];
+            }
+        }
+        if (a.nsrc > 0) {
+            __syncthreads();
+            const float *q = a.src_data + (int64_t)t * a.nsrc;
+            for (int e = tid; e < a.nsrc * 4; e += 1024) {
+                const int s = e >> 2, c = e & 3;
+                const int64_t rel = a.src_base[s] - off0;
+                const int x = (int)(rel % px) + (c & 1), z = (int)(rel / px) + (c >> 1);
+                const int64_t gi = off0 + (int64_t)z * px + x;
+                atomicAdd(&cur[z * lw + x], a.src_w[s * 4 + c] * q[s] * fast_rcp(a.m[gi]));
+            }
+        }
+        __syncthreads();
+        if (t >= a.time_M - 2) {
+            float *un = a.u + (int64_t)((t + 1) % 3) * a.slot;
+            for (int i = tid; i < n; i += 1024) un[goff(i)] = cur[li(i)];
+        }
+        if (a.nrec > 0) {
+            float *rr = a.rec_data + (int64_t)t * a.nrec;
+            for (int e = tid; e < a.nrec * 4; e += 1024) {
+                const int r = e >> 2, c = e & 3;
+                const int64_t rel = a.rec_base[r] - off0;
+                const int x = (int)(rel % px) + (c & 1), z = (int)(rel / px) + (c >> 1);
+                float val = a.rec_w[r * 4 + c] * cur[z * lw + x];
+                // groups of 4 lanes are aligned in the wavefront
+                val += __shfl_xor(val, 1);
+                val += __shfl_xor(val, 2);
+                if (c == 0) rr[r] = val;
+            }
+        }
+        // LDS is only read from here to the first barrier of the next step
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+template <int NDIM, int R>
+static hipError_t launch_iso_naive(const IsoArgs &a, hipStream_t s) {
+    if (NDIM == 3) {
+        dim3 blk(64, 4, 1), grd((a.g.nx + 63) / 64, (a.g.ny + 3) / 4, a.g.nz);
+        hipLaunchKernelGGL((iso_naive<NDIM, R>), grd, blk, 0, s, a);
+    } else {
+        dim3 blk(64, 4, 1), grd((a.g.nx + 63) / 64, (a.g.nz + 3) / 4, 1);
+        hipLaunchKernelGGL((iso_naive<NDIM, R>), grd, blk, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+// Tile shapes are (NY y-columns per thread, BY wavefronts per workgroup, z-chunk
+// ZC, prefetch PF); tile = 64 x (NY * BY).  Environment overrides for tuning:
+//   FDW_ISO_TILE="NY,ZC,PF,BY"   FDW_TTI_TILE="NY1,BY1,NY2,BY2,ZC"
+struct IsoShape {
+    int ny, zc, pf, by;
+};
+
+static IsoShape iso_stream_shape(const Geom &g) {
+    IsoShape sh{4, 16, 1, 4};
+    if (const char *e = std::getenv("FDW_ISO_TILE")) {
+        int a = 0, b = 0, c = 1, d = 4;
+        const int n = std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d);
+        if (n >= 2 && (a == 1 || a == 2 || a == 4) && b > 0 && (c == 1 || c == 2) && (d == 4 || d == 8))
+            sh = IsoShape{a, b, c, d};
+    }
+    if (sh.zc > g.nz) sh.zc = g.nz;
+    return sh;
+}
+
+template <int R, int NY, int PF, int BY>
+static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t s) {
+    IsoOp op;
+    op.c = a.c;
+    op.eta = DampTables{a.eta_x, a.eta_y, a.eta_z};
+    op.dt2 = a.dt2;
+    op.src = a.src;
+    op.u_next = a.u_next;
+    StreamFields<1, 2> F;
+    F.q[0] = a.u_cur;
+    F.p[0] = a.u_prev;
+    F.p[1] = a.m;
+    F.pout[0] = 0.0f;
+    F.pout[1] = 1.0f;
+    return launch_stream3d<R, NY, PF, BY>(op, F, a.g, zc, s);
+}
+
+template <int R, int NY, int PF>
+static hipError_t launch_iso3d_stream_by(const IsoArgs &a, const IsoShape &sh, hipStream_t s) {
+    if (sh.by == 8) return launch_iso3d_stream_cfg<R, NY, PF, 8>(a, sh.zc, s);
+    return launch_iso3d_stream_cfg<R, NY, PF, 4>(a, sh.zc, s);
+}
+
+template <int R, int NY>
+static hipError_t launch_iso3d_stream_ny(const IsoArgs &a, const IsoShape &sh, hipStream_t s) {
+    if (sh.pf == 2) return launch_iso3d_stream_by<R, NY, 2>(a, sh, s);
+    return launch_iso3d_stream_by<R, NY, 1>(a, sh, s);
+}
+
+// Tuning variants are instantiated for R = 4 (space order 8) only; other
+// orders use the default shape.
+template <int R>
+static hipError_t launch_iso3d_stream(const IsoArgs &a, hipStream_t s) {
+    const IsoShape sh = iso_stream_shape(a.g);
+    if constexpr (R == 4) {
+        if (sh.ny == 1) return launch_iso3d_stream_ny<R, 1>(a, sh, s);
+        if (sh.ny == 2) return launch_iso3d_stream_ny<R, 2>(a, sh, s);
+        return launch_iso3d_stream_ny<R, 4>(a, sh, s);
+    } else {
+        return launch_iso3d_stream_cfg<R, 4, 1, 4>(a, sh.zc, s);
+    }
+}
+
+hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream_t s) {
+#define ISO_S3(r) launch_iso3d_stream<r>(a, s)
+    if (ndim == 3 && v == IsoVariant::Stream) { FDW_DISPATCH_R(R, ISO_S3) }
+#undef ISO_S3
+#define ISO_N3(r) launch_iso_naive<3, r>(a, s)
+#define ISO_N2(r) launch_iso_naive<2, r>(a, s)
+    if (ndim == 3) { FDW_DISPATCH_R(R, ISO_N3) }
+    FDW_DISPATCH_R(R, ISO_N2)
+#undef ISO_N3
+#undef ISO_N2
+}
+
+template <int R, bool HALO>
+static hipError_t launch_iso2d_persistent_h(const Persist2DArgs &a, size_t lds, hipStream_t s) {
+    const int ppt = (a.g.nx * a.g.nz + 1023) / 1024;
+#define P2D(PPT_)                                                                                       \
+    {                                                                                                   \
+        hipError_t e = hipFuncSetAttribute((const void *)iso2d_persistent<R, PPT_, HALO>,              \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
+        if (e != hipSuccess) return e;                                                                  \
+        hipLaunchKernelGGL((iso2d_persistent<R, PPT_, HALO>), dim3(1), dim3(1024), lds, s, a);         \
+        return hipGetLastError();                                                                       \
+    }
+    if (ppt <= 8) P2D(8)
+    if (ppt <= 16) P2D(16)
+    if (ppt <= 24) P2D(24)
+    if (ppt <= 40) P2D(40)
+#undef P2D
+    return hipErrorInvalidValue;
+}
+
+template <int R>
+static hipError_t launch_iso2d_persistent_r(const Persist2DArgs &a, hipStream_t s) {
+    const size_t halo = sizeof(float) * (size_t)(a.g.nx + 2 * R) * (size_t)(a.g.nz + 2 * R);
+    if (halo <= (size_t)kPersist2DMaxLds) return launch_iso2d_persistent_h<R, true>(a, halo, s);
+    return launch_iso2d_persistent_h<R, false>(a, sizeof(float) * (size_t)a.g.nx * a.g.nz, s);
+}
+
+hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s) {
+    if ((size_t)a.g.nx * a.g.nz * sizeof(float) > (size_t)kPersist2DMaxLds) return hipErrorInvalidValue;
+#define P2R(r) launch_iso2d_persistent_r<r>(a, s)
+    FDW_DISPATCH_R(R, P2R)
+#undef P2R
+}
+
+const char *iso_kernel_name(int ndim, IsoVariant v) {
+    if (ndim == 3 && v == IsoVariant::Stream) {
+        static char buf[96];
+        Geom g{};
+        g.nz = 1 << 30;
+        const IsoShape sh = iso_stream_shape(g);
+        std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x%d (%d waves) zchunk=%d prefetch=%d", sh.by * sh.ny,
+                      sh.by, sh.zc, sh.pf);
+        return buf;
+    }
+    return ndim == 3 ? "iso_naive<3>" : "iso_naive<2>";
+}
+
+}  // namespace fdw

@@ -1,0 +1,88 @@
+// Sparse-point kernels (gfx950): receiver interpolation (gather with
+// cross-lane reductions) and source injection (scatter with atomics), and the
+// halo-zeroing kernel.  Paper: arXiv 1807.03032, Section 3.3 (eq. interp,
+// Listing finject).
+#include "fdw_device.h"
+
+namespace fdw {
+
+// ---------------------------------------------------------------------------
+// Sparse kernels.  One group of ncorner lanes per sparse point: lane c owns
+// corner c; interpolation reduces the group's products with cross-lane
+// shuffles; injection scatters with atomics (sources may share points).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t corner_offset(const SparseArgs &a, int c) {
+    return ((c & 1) ? a.cstride[0] : 0) + ((c & 2) ? a.cstride[1] : 0) + ((c & 4) ? a.cstride[2] : 0);
+}
+
+__global__ void __launch_bounds__(256) interp_kernel(SparseArgs a) {
+    const int lane = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = lane / a.ncorner;
+    const int c = lane % a.ncorner;
+    float v = 0.0f;
+    if (p < a.npoint) v = a.w[(int64_t)p * a.ncorner + c] * a.field[a.base[p] + corner_offset(a, c)];
+    // groups of 4 or 8 lanes are aligned inside the 64-wide wavefront
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    if (a.ncorner == 8) v += __shfl_xor(v, 4);
+    if (p < a.npoint && c == 0) a.rec_row[p] = v;
+}
+
+__global__ void __launch_bounds__(256) inject_kernel(SparseArgs a) {
+    const int lane = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = lane / a.ncorner;
+    const int c = lane % a.ncorner;
+    if (p >= a.npoint) return;
+    const int64_t i = a.base[p] + corner_offset(a, c);
+    atomicAdd(a.field + i, a.w[(int64_t)p * a.ncorner + c] * a.q_row[p] * fast_rcp(a.m[i]));
+}
+
+// Writes zero to every element of one slot outside the domain.
+__global__ void __launch_bounds__(256) zero_halo_kernel(int ndim, Geom g, int R, int64_t pitch_x,
+                                                        int64_t pitch_y, int64_t planes, float *base) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = pitch_x * pitch_y * planes;
+    if (e >= total) return;
+    const int64_t xx = e % pitch_x;
+    const int64_t row = e / pitch_x;
+    const int64_t x = xx - (g.off0 % pitch_x);
+    bool inside = x >= 0 && x < g.nx;
+    if (ndim == 3) {
+        const int64_t y = row % pitch_y - R;
+        const int64_t z = row / pitch_y - R;
+        inside = inside && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+    } else {
+        const int64_t z = row - R;
+        inside = inside && z >= 0 && z < g.nz;
+    }
+    if (!inside) base[e] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_inject(const SparseArgs &a, hipStream_t s) {
+    if (a.npoint <= 0) return hipSuccess;
+    const int64_t lanes = (int64_t)a.npoint * a.ncorner;
+    hipLaunchKernelGGL(inject_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(const SparseArgs &a, hipStream_t s) {
+    if (a.npoint <= 0) return hipSuccess;
+    const int64_t lanes = (int64_t)a.npoint * a.ncorner;
+    hipLaunchKernelGGL(interp_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_halo(int ndim, const Geom &g, int R, int64_t pitch_x, int64_t pitch_y, int64_t planes,
+                            float *base, hipStream_t s) {
+    const int64_t total = pitch_x * pitch_y * planes;
+    hipLaunchKernelGGL(zero_halo_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ndim, g, R,
+                       pitch_x, pitch_y, planes, base);
+    return hipGetLastError();
+}
+
+}  // namespace fdw

@@ -1,0 +1,295 @@
+// TTI pseudo-acoustic step kernels (gfx950): stage 1 (rotated gradients)
+// and stage 2 (rotated second derivatives, Laplacian, coupled update) on the
+// z-streaming engine, plus the one-thread-per-point schedule.
+// Paper: arXiv 1807.03032, Section 7.2 (two coupled acoustic equations with
+// Laplacians built from rotated first derivatives) and Section 6 (the
+// producer/consumer temporaries that the two-stage split corresponds to).
+#include "fdw_device.h"
+
+namespace fdw {
+
+// Unit normal of the TTI symmetry axis: (sin th cos ph, sin th sin ph, cos th)
+// in 3D, (sin th, cos th) over (x, z) in 2D.
+template <int NDIM>
+__device__ __forceinline__ void tti_normal(const TtiArgs &a, int64_t i, float &nx, float &ny, float &nz) {
+    float st, ct;
+    sincosf(a.theta[i], &st, &ct);
+    if (NDIM == 3) {
+        float sp, cp;
+        sincosf(a.phi[i], &sp, &cp);
+        nx = st * cp;
+        ny = st * sp;
+        nz = ct;
+    } else {
+        nx = st;
+        ny = 0.0f;
+        nz = ct;
+    }
+}
+
+// n . grad f at element i (centred first derivatives of order 2R).
+template <int NDIM, int R>
+__device__ __forceinline__ float rot_grad(const float *f, int64_t i, const Geom &g, const Coefs &c, float nx,
+                                          float ny, float nz) {
+    float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+        dx += c.w1[0][k] * (f[i + k] - f[i - k]);
+        dz += c.w1[2][k] * (f[i + k * g.sz] - f[i - k * g.sz]);
+        if (NDIM == 3) dy += c.w1[1][k] * (f[i + k * g.sy] - f[i - k * g.sy]);
+    }
+    float r = nx * dx + nz * dz;
+    if (NDIM == 3) r += ny * dy;
+    return r;
+}
+
+// TTI stage 1: gp = n . grad p, gr = n . grad r on every domain point.
+template <int NDIM, int R>
+__global__ void __launch_bounds__(256) tti_naive_stage1(TtiArgs a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
+    const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+    const int64_t i = a.g.off0 + (int64_t)z * a.g.sz + (int64_t)y * a.g.sy + x;
+    float nx, ny, nz;
+    tti_normal<NDIM>(a, i, nx, ny, nz);
+    a.gp[i] = rot_grad<NDIM, R>(a.p_cur, i, a.g, a.c, nx, ny, nz);
+    a.gr[i] = rot_grad<NDIM, R>(a.r_cur, i, a.g, a.c, nx, ny, nz);
+}
+
+// TTI stage 2: H p = n . grad gp, H r = n . grad gr, L p, coupled update.
+template <int NDIM, int R>
+__global__ void __launch_bounds__(256) tti_naive_stage2(TtiArgs a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
+    const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+    const int64_t i = a.g.off0 + (int64_t)z * a.g.sz + (int64_t)y * a.g.sy + x;
+    float nx, ny, nz;
+    tti_normal<NDIM>(a, i, nx, ny, nz);
+    const float hp = rot_grad<NDIM, R>(a.gp, i, a.g, a.c, nx, ny, nz);
+    const float hr = rot_grad<NDIM, R>(a.gr, i, a.g, a.c, nx, ny, nz);
+    const float pc = a.p_cur[i];
+    const float lap = laplacian_at<NDIM, R>(a.p_cur, i, a.g, a.c);
+    const float A = lap - hp;
+    const float B = hr;
+    const float s = sqrtf(1.0f + 2.0f * a.delta[i]);
+    const float rm = fast_rcp(a.m[i]);
+    const float cdt = a.dt2 * rm;
+    const float d = damp_at(a.eta_x, a.eta_y, a.eta_z, NDIM, x, y, z);
+    float pn = leapfrog(pc, a.p_prev[i], cdt * ((1.0f + 2.0f * a.eps[i]) * A + s * B), d);
+    float rn = leapfrog(a.r_cur[i], a.r_prev[i], cdt * (s * A + B), d);
+    if (a.src.n) {
+        pn = fused_inject(a.src, NDIM, x, y, z, rm, pn);
+        rn = fused_inject(a.src, NDIM, x, y, z, rm, rn);
+    }
+    a.p_next[i] = pn;
+    a.r_next[i] = rn;
+}
+
+// n = (sin th cos ph, sin th sin ph, cos th) with the hardware sin/cos
+// (arguments in [0, 2 pi) after range reduction by the builtin).
+__device__ __forceinline__ void tti_normal3(float th, float ph, float &nx, float &ny, float &nz) {
+    const float st = __sinf(th), ct = __cosf(th), sp = __sinf(ph), cp = __cosf(ph);
+    nx = st * cp;
+    ny = st * sp;
+    nz = ct;
+}
+
+// ---- TTI stage 1: stencil fields p, r; pointwise theta, phi ------------------
+//   gp = n . grad p,  gr = n . grad r   (order-2R centred first derivatives)
+struct TtiS1Op {
+    Coefs c;
+    float *gp, *gr;
+    __device__ __forceinline__ bool begin_tile(int, int, int, int, int, int) const { return false; }
+    __device__ __forceinline__ float begin_column(int, int) const { return 0.0f; }
+    __device__ __forceinline__ float begin_plane(int) const { return 0.0f; }
+    template <int R, class P>
+    __device__ __forceinline__ void point(const P &pt, bool, float, bool live) const {
+        float nx, ny, nz;
+        tti_normal3(pt.p(0), pt.p(1), nx, ny, nz);
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+#pragma unroll
+            for (int k = 1; k <= R; ++k) {
+                dx += c.w1[0][k] * (pt.qx(f, k) - pt.qx(f, -k));
+                dy += c.w1[1][k] * (pt.qy(f, k) - pt.qy(f, -k));
+                dz += c.w1[2][k] * (pt.qz(f, k) - pt.qz(f, -k));
+            }
+            const float gv = nx * dx + ny * dy + nz * dz;
+            if (live) (f == 0 ? gp : gr)[pt.off] = gv;
+        }
+    }
+};
+
+// ---- TTI stage 2: stencil fields gp, gr, p; pointwise p(t-1), r(t), r(t-1),
+// m, eps, delta, theta, phi --------------------------------------------------
+//   Hp = n . grad gp, Hr = n . grad gr, A = L p - Hp, B = Hr
+//   p+ from (1 + 2 eps) A + sqrt(1 + 2 delta) B, r+ from sqrt(1 + 2 delta) A + B
+struct TtiS2Op {
+    Coefs c;
+    DampTables eta;
+    float dt2;
+    FusedSrc src;
+    float *p_next, *r_next;
+    __device__ __forceinline__ bool begin_tile(int x0, int tx, int y0, int ty, int z0, int z1) const {
+        return src_in_tile(src, x0, tx, y0, ty, z0, z1);
+    }
+    __device__ __forceinline__ float begin_column(int x, int y) const { return eta.ex[x] + eta.ey[y]; }
+    __device__ __forceinline__ float begin_plane(int z) const { return eta.ez[z]; }
+    template <int R, class P>
+    __device__ __forceinline__ void point(const P &pt, bool src_here, float a, bool live) const {
+        float nx, ny, nz;
+        tti_normal3(pt.p(6), pt.p(7), nx, ny, nz);
+        float h[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+#pragma unroll
+            for (int k = 1; k <= R; ++k) {
+                dx += c.w1[0][k] * (pt.qx(f, k) - pt.qx(f, -k));
+                dy += c.w1[1][k] * (pt.qy(f, k) - pt.qy(f, -k));
+                dz += c.w1[2][k] * (pt.qz(f, k) - pt.qz(f, -k));
+            }
+            h[f] = nx * dx + ny * dy + nz * dz;
+        }
+        const float pc = pt.qz(2, 0);
+        const float p2 = 2.0f * pc;
+        float lap = 0.0f;
+#pragma unroll
+        for (int k = 1; k <= R; ++k) {
+            lap += c.w2[2][k] * ((pt.qz(2, k) + pt.qz(2, -k)) - p2);
+            lap += c.w2[0][k] * ((pt.qx(2, k) + pt.qx(2, -k)) - p2);
+            lap += c.w2[1][k] * ((pt.qy(2, k) + pt.qy(2, -k)) - p2);
+        }
+        const float A = lap - h[0];
+        const float B = h[1];
+        const float sd = __builtin_sqrtf(1.0f + 2.0f * pt.p(5));
+        const float rm = fast_rcp(pt.p(3));
+        const float cdt = dt2 * rm;
+        float pn = leapfrog(pc, pt.p(0), cdt * ((1.0f + 2.0f * pt.p(4)) * A + sd * B), a);
+        float rn = leapfrog(pt.p(1), pt.p(2), cdt * (sd * A + B), a);
+        if (src_here) {
+            pn = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, pn);
+            rn = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, rn);
+        }
+        if (live) {
+            p_next[pt.off] = pn;
+            r_next[pt.off] = rn;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+template <int NDIM, int R>
+static hipError_t launch_tti_naive(const TtiArgs &a, hipStream_t s) {
+    dim3 blk(64, 4, 1);
+    dim3 grd = NDIM == 3 ? dim3((a.g.nx + 63) / 64, (a.g.ny + 3) / 4, a.g.nz)
+                         : dim3((a.g.nx + 63) / 64, (a.g.nz + 3) / 4, 1);
+    hipLaunchKernelGGL((tti_naive_stage1<NDIM, R>), grd, blk, 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((tti_naive_stage2<NDIM, R>), grd, blk, 0, s, a);
+    return hipGetLastError();
+}
+
+struct TtiShape {
+    int ny1, by1, ny2, by2, zc;
+};
+
+static TtiShape tti_stream_shape(const Geom &g) {
+    TtiShape sh{2, 8, 1, 8, 32};
+    if (const char *e = std::getenv("FDW_TTI_TILE")) {
+        int a = 0, b = 0, c = 0, d = 0, z = 0;
+        if (std::sscanf(e, "%d,%d,%d,%d,%d", &a, &b, &c, &d, &z) == 5 && (a == 1 || a == 2) && (b == 4 || b == 8) &&
+            (c == 1 || c == 2) && (d == 4 || d == 8) && z > 0)
+            sh = TtiShape{a, b, c, d, z};
+    }
+    if (sh.zc > g.nz) sh.zc = g.nz;
+    return sh;
+}
+
+template <int R, int NY, int BY, class Op, int NQ, int NP>
+static hipError_t launch_tti_stage(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s) {
+    return launch_stream3d<R, NY, 1, BY>(op, F, g, zc, s);
+}
+
+// Tuning variants are instantiated for R = 6 (space order 12) only; other
+// orders use (NY, BY) = (2, 8) for stage 1 and (1, 8) for stage 2.
+template <int R, class Op, int NQ, int NP>
+static hipError_t launch_tti_stage_shape(int ny, int by, const Op &op, const StreamFields<NQ, NP> &F, const Geom &g,
+                                         int zc, hipStream_t s) {
+    if constexpr (R == 6) {
+        if (ny == 2)
+            return by == 8 ? launch_tti_stage<R, 2, 8>(op, F, g, zc, s) : launch_tti_stage<R, 2, 4>(op, F, g, zc, s);
+        return by == 8 ? launch_tti_stage<R, 1, 8>(op, F, g, zc, s) : launch_tti_stage<R, 1, 4>(op, F, g, zc, s);
+    } else {
+        if (NQ == 2) return launch_tti_stage<R, 2, 8>(op, F, g, zc, s);
+        return launch_tti_stage<R, 1, 8>(op, F, g, zc, s);
+    }
+}
+
+template <int R>
+static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s) {
+    const TtiShape sh = tti_stream_shape(a.g);
+    TtiS1Op o1;
+    o1.c = a.c;
+    o1.gp = a.gp;
+    o1.gr = a.gr;
+    StreamFields<2, 2> F1;
+    F1.q[0] = a.p_cur;
+    F1.q[1] = a.r_cur;
+    F1.p[0] = a.theta;
+    F1.p[1] = a.phi;
+    F1.pout[0] = F1.pout[1] = 0.0f;
+    hipError_t e = launch_tti_stage_shape<R>(sh.ny1, sh.by1, o1, F1, a.g, sh.zc, s);
+    if (e != hipSuccess) return e;
+    TtiS2Op o2;
+    o2.c = a.c;
+    o2.eta = DampTables{a.eta_x, a.eta_y, a.eta_z};
+    o2.dt2 = a.dt2;
+    o2.src = a.src;
+    o2.p_next = a.p_next;
+    o2.r_next = a.r_next;
+    StreamFields<3, 8> F2;
+    F2.q[0] = a.gp;
+    F2.q[1] = a.gr;
+    F2.q[2] = a.p_cur;
+    const float *pw[8] = {a.p_prev, a.r_cur, a.r_prev, a.m, a.eps, a.delta, a.theta, a.phi};
+    for (int i = 0; i < 8; ++i) {
+        F2.p[i] = pw[i];
+        F2.pout[i] = 0.0f;
+    }
+    F2.pout[3] = 1.0f;  // m
+    return launch_tti_stage_shape<R>(sh.ny2, sh.by2, o2, F2, a.g, sh.zc, s);
+}
+
+hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s) {
+#define TTI_S3(r) launch_tti3d_stream<r>(a, s)
+    if (ndim == 3 && v == TtiVariant::Stream) { FDW_DISPATCH_R(R, TTI_S3) }
+#undef TTI_S3
+#define TTI_N3(r) launch_tti_naive<3, r>(a, s)
+#define TTI_N2(r) launch_tti_naive<2, r>(a, s)
+    if (ndim == 3) { FDW_DISPATCH_R(R, TTI_N3) }
+    FDW_DISPATCH_R(R, TTI_N2)
+#undef TTI_N3
+#undef TTI_N2
+}
+const char *tti_kernel_name(int ndim, TtiVariant v) {
+    if (ndim == 3 && v == TtiVariant::Stream) {
+        static char buf[96];
+        Geom g{};
+        g.nz = 1 << 30;
+        const TtiShape sh = tti_stream_shape(g);
+        std::snprintf(buf, sizeof(buf), "tti3d_stream stage1 tile=64x%d stage2 tile=64x%d zchunk=%d", sh.by1 * sh.ny1,
+                      sh.by2 * sh.ny2, sh.zc);
+        return buf;
+    }
+    return ndim == 3 ? "tti_naive_stage1+2<3>" : "tti_naive_stage1+2<2>";
+}
+
+}  // namespace fdw

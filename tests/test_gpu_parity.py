@@ -240,3 +240,38 @@ def test_config_3d_tti_512_full_sampled(torch_dev):
     say(prob.name, "full")
     gf, gtr, _ = gpu_run(prob, torch_dev)
     _sampled_check("3d_tti_512", prob, gf, gtr)
+
+
+def test_large_2d_grid_uses_per_step_kernel(torch_dev):
+    """A 2D grid too large for the LDS-resident kernel (per-step launches)."""
+    src = np.array([[1200.0, 900.0], [2500.5, 1700.25]])
+    rec = np.concatenate([src + d for d in ([35.0, 0.0], [0.0, -42.5], [-27.3, 31.1], [12.0, 12.0])])
+    prob = W.small_problem("iso", (401, 301), 8, nt=40, seed=31, src_at=src, rec_coords=rec, nbl=6)
+    say("large 2D", prob.shape)
+    gf, gtr, desc = gpu_run(prob, torch_dev)
+    assert "persistent" not in desc
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+
+
+def test_small_2d_grid_uses_persistent_kernel(torch_dev):
+    prob = W.small_problem("iso", (120, 95), 12, nt=60, seed=32, nsrc=6, nrec=30, nbl=8)
+    say("persistent 2D", prob.shape)
+    gf, gtr, desc = gpu_run(prob, torch_dev)
+    assert "persistent" in desc
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+
+
+@pytest.mark.parametrize("kind,shape", [("iso", (35, 30, 26)), ("tti", (33, 28, 25)), ("iso", (60, 41)),
+                                        ("tti", (48, 39))])
+def test_one_thread_per_point_schedule(torch_dev, monkeypatch, kind, shape):
+    """FDW_KERNEL=naive selects the one-thread-per-point kernels at operator
+    creation; they must agree with the oracle as well."""
+    monkeypatch.setenv("FDW_KERNEL", "naive")
+    prob = W.small_problem(kind, shape, 8, nt=20, seed=33, nrec=10)
+    say("naive schedule", kind, shape)
+    gf, gtr, desc = gpu_run(prob, torch_dev)
+    assert "naive" in desc
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
