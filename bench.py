@@ -36,6 +36,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps of the bounded CPU sample")
     ap.add_argument("--tti", action="store_true", help="also time the 512^3 TTI so=12 operator")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (counter calibration under rocprofv3 --pmc)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE counter CSVs into profiles/traffic.json")
     return ap.parse_args()
 
 
@@ -111,19 +115,122 @@ def cpu_baseline(prob, nsteps):
                       f"({wall:.1f} s wall)"}
 
 
-def roofline(prob, kms, launches, alg_bytes):
+# ---------------------------------------------------------------------------
+# Measured HBM traffic of the dominant kernels.  FETCH_SIZE / WRITE_SIZE are
+# read per dispatch with rocprofv3 --pmc (one counter per run) and scaled by
+# what the same counter reads for a plain device copy of known size run in the
+# same process.  The summary is keyed by the operator description and a hash
+# of the kernel sources, so a changed kernel reports traffic = null.
+# ---------------------------------------------------------------------------
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = {
+    "iso": ["fdw_device.h", "fdw_iso.hip", "fdw_internal.h"],
+    "tti": ["fdw_device.h", "fdw_tti.hip", "fdw_internal.h"],
+}
+CALIB_BYTES = 256 * 1024 * 1024
+
+
+def source_hash(kind):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, "paper_1807_03032_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def calib_copy(device):
+    """Plain streaming kernel of known size: b = -a over 256 MiB (reads and
+    writes 256 MiB each); its distinctive name (neg_kernel) identifies it in
+    the counter CSVs."""
+    import torch
+
+    a = torch.ones(CALIB_BYTES // 4, device=device)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize(device)
+
+
+def summarize_traffic(fetch_csv, write_csv):
+    """Median KiB per dispatch of every fdw kernel, scaled by the copy calibration."""
+    import csv
+    import statistics
+
+    def per_dispatch(path):
+        agg = {}
+        for r in csv.DictReader(open(path)):
+            k = int(r["Dispatch_Id"])
+            agg.setdefault(k, [r["Kernel_Name"], 0.0])
+            agg[k][1] += float(r["Counter_Value"])
+        return agg
+
+    out = {}
+    fetch, write = per_dispatch(fetch_csv), per_dispatch(write_csv)
+    # calibration: the median reading of the 256 MiB neg_kernel dispatches
+    def cal(agg):
+        vals = [v for n, v in agg.values() if "neg_kernel" in n]
+        return statistics.median(vals)
+
+    factors = {"fetch": (CALIB_BYTES / 1024.0) / cal(fetch), "write": (CALIB_BYTES / 1024.0) / cal(write)}
+    for counter, agg in (("fetch", fetch), ("write", write)):
+        kern = {}
+        for n, v in agg.values():
+            if "fdw::" in n:
+                kern.setdefault(n, []).append(v)
+        for n, vals in kern.items():
+            e = out.setdefault(n, {})
+            e[f"{counter}_kib_median"] = statistics.median(vals)
+            e[f"{counter}_factor"] = round(factors[counter], 4)
+            e[f"{counter}_bytes"] = statistics.median(vals) * 1024.0 * factors[counter]
+            e["dispatches"] = len(vals)
+    return out
+
+
+def load_traffic(kind, desc):
+    """Measured bytes per launch of this operator's kernels, or None."""
+    try:
+        db = json.load(open(TRAFFIC_JSON))
+    except (OSError, ValueError):
+        return None
+    e = db.get(desc)
+    if not e or e.get("source_hash") != source_hash(kind):
+        return None
+    return e.get("bytes_per_launch")
+
+
+def roofline(prob, kms, launches, alg_bytes, traffic=None):
     if launches <= 0 or kms <= 0:
         return None
     avg_s = kms / launches / 1e3
     per_launch = alg_bytes * prob.npoints
     achieved = per_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic) if traffic is not None else None,
+            "algorithmic_bytes": round(per_launch),
             "kernel_avg_us": round(avg_s * 1e6, 2), "bytes_per_point": alg_bytes}
 
 
 def main():
     args = parse()
+    if args.traffic_from:
+        ops = json.load(open(args.traffic_from[0] + ".ops.json")) if os.path.exists(
+            args.traffic_from[0] + ".ops.json") else None
+        kern = summarize_traffic(*args.traffic_from)
+        print(json.dumps(kern, indent=1))
+        if ops:
+            db = json.load(open(TRAFFIC_JSON)) if os.path.exists(TRAFFIC_JSON) else {}
+            for op in ops:
+                names = [n for n in kern if any(s in n for s in op["kernel_match"])]
+                tot = sum(kern[n]["fetch_bytes"] + kern[n]["write_bytes"] for n in names)
+                db[op["desc"]] = {"source_hash": op["source_hash"], "kernels": {n: kern[n] for n in names},
+                                  "bytes_per_launch": tot, "fetch_csv": os.path.basename(args.traffic_from[0]),
+                                  "write_csv": os.path.basename(args.traffic_from[1])}
+            os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+            json.dump(db, open(TRAFFIC_JSON, "w"), indent=1, sort_keys=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -137,6 +244,8 @@ def main():
         sys.exit(2)
     fdw.load()
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        calib_copy(dev)
     prob = W.config_3d_iso_256(nt=max(1000, args.steps) if args.steps > 1000 else 1000)
     steps, warmup = args.steps, args.warmup
     wall, kms, launches, desc, alg_bytes, tr, f = time_shot(prob, steps, warmup, dev)
@@ -157,8 +266,9 @@ def main():
         "config": {"workload": "3D isotropic acoustic 256^3, h=10 m, v 1500/2500 m/s two-layer, so=8, nbl=40, "
                                "15 Hz Ricker source, 256x256 receiver plane (trilinear), 1000 steps",
                    "grid": list(prob.shape), "space_order": prob.so, "nt": prob.nt, "kernel": desc},
-        "roofline": roofline(prob, kms, launches, alg_bytes),
+        "roofline": roofline(prob, kms, launches, alg_bytes, load_traffic("iso", desc)),
     }
+    ops_seen = [{"desc": desc, "source_hash": source_hash("iso"), "kernel_match": ["IsoOp", "iso_naive"]}]
     par = parity_vs_stored("3d_iso_256", prob, steps, tr, f)
     if par is not None:
         line["parity_rel_l2_sampled"] = par
@@ -167,12 +277,15 @@ def main():
         w2, k2, l2, d2, b2, tr2, f2 = time_shot(pt, pt.nt, 20, dev)
         line["tti"] = {"workload": "3D TTI 512^3, h=12.5 m, so=12, nbl=40, 800 steps", "kernel": d2,
                        "value": round(pt.npoints * pt.nt / w2 / 1e9, 3), "unit": "GPts/s",
-                       "roofline": roofline(pt, k2, l2, b2)}
+                       "roofline": roofline(pt, k2, l2, b2, load_traffic("tti", d2))}
+        ops_seen.append({"desc": d2, "source_hash": source_hash("tti"), "kernel_match": ["TtiS1Op", "TtiS2Op", "tti_naive"]})
         p2 = parity_vs_stored("3d_tti_512", pt, pt.nt, tr2, f2)
         if p2 is not None:
             line["tti"]["parity_rel_l2_sampled"] = p2
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
+    if os.environ.get("FDW_BENCH_OPS_OUT"):
+        json.dump(ops_seen, open(os.environ["FDW_BENCH_OPS_OUT"], "w"))
     print(json.dumps(line), flush=True)
 
 

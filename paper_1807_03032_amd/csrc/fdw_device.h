@@ -309,11 +309,12 @@ struct DampTables {
 };
 
 template <int R, int NY, int PF, int BY, int NQ, int NP, class Op>
-static hipError_t launch_stream3d(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s) {
+static hipError_t launch_stream3d(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s,
+                                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + BY * NY - 1) / (BY * NY), ntz = (g.nz + zc - 1) / zc;
     const int64_t nb = (int64_t)ntx * nty * ntz;
-    hipLaunchKernelGGL((stream3d<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)nb), dim3(64 * BY), 0, s, op, F, g, zc,
-                       ntx, nty);
+    hipExtLaunchKernelGGL((stream3d<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)nb), dim3(64 * BY), 0, s, e0, e1, 0, op,
+                          F, g, zc, ntx, nty);
     return hipGetLastError();
 }
 

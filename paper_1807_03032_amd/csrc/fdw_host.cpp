@@ -712,20 +712,14 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         pa.rec_base = op->d_rec_base;
         pa.rec_w = op->d_rec_w;
         pa.rec_data = nrec > 0 ? d.rec->data : nullptr;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
+        LaunchEvents ev;
         if (op->timing) {
-            int st = timing_event_pair(op, &e0, &e1);
+            int st = timing_event_pair(op, &ev.start, &ev.stop);
             if (st) return st;
-            hipError_t er = hipEventRecord(e0, s);
-            if (er != hipSuccess) return fail_hip(er, "operator_apply: hipEventRecord");
         }
-        hipError_t e = launch_iso2d_persistent(op->R, pa, s);
+        hipError_t e = launch_iso2d_persistent(op->R, pa, s, ev);
         if (e != hipSuccess) return fail_hip(e, "operator_apply: persistent 2D launch");
-        if (op->timing) {
-            hipError_t er = hipEventRecord(e1, s);
-            if (er != hipSuccess) return fail_hip(er, "operator_apply: hipEventRecord");
-            op->acc_launches++;
-        }
+        if (op->timing) op->acc_launches++;
         return FDW_OK;
     }
     for (int t = time_m; t <= time_M; ++t) {
@@ -735,12 +729,10 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             fs = op->fsrc_template;
             fs.q = d.src->data + (int64_t)t * nsrc;
         }
-        hipEvent_t e0 = nullptr, e1 = nullptr;
+        LaunchEvents ev;
         if (op->timing) {
-            int st = timing_event_pair(op, &e0, &e1);
+            int st = timing_event_pair(op, &ev.start, &ev.stop);
             if (st) return st;
-            hipError_t er = hipEventRecord(e0, s);
-            if (er != hipSuccess) return fail_hip(er, "operator_apply: hipEventRecord");
         }
         hipError_t e;
         float *next_field;
@@ -757,7 +749,7 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             a.dt2 = op->dt2;
             a.c = op->coefs;
             a.src = fs;
-            e = launch_iso(op->ndim, op->R, op->iso_v, a, s);
+            e = launch_iso(op->ndim, op->R, op->iso_v, a, s, ev);
             next_field = a.u_next;
         } else {
             TtiArgs a{};
@@ -781,15 +773,11 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             a.dt2 = op->dt2;
             a.c = op->coefs;
             a.src = fs;
-            e = launch_tti(op->ndim, op->R, op->tti_v, a, s);
+            e = launch_tti(op->ndim, op->R, op->tti_v, a, s, ev);
             next_field = a.p_next;
         }
         if (e != hipSuccess) return fail_hip(e, "operator_apply: stencil launch");
-        if (op->timing) {
-            hipError_t er = hipEventRecord(e1, s);
-            if (er != hipSuccess) return fail_hip(er, "operator_apply: hipEventRecord");
-            op->acc_launches++;
-        }
+        if (op->timing) op->acc_launches++;
         if (nsrc > 0 && !op->src_fused) {
             inj.q_row = d.src->data + (int64_t)t * nsrc;
             inj.field = next_field;

@@ -2,6 +2,7 @@
 // kernels (fdw_kernels.hip).  Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -107,12 +108,20 @@ constexpr int kPersist2DMaxLds = 152 * 1024;
 enum class IsoVariant { Naive = 0, Stream = 1 };
 enum class TtiVariant { Naive = 0, Stream = 1 };
 
-// Launchers (fdw_kernels.hip).  Each returns the hipError_t of its launch.
-hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream_t s);
-hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s);
+// Optional events recorded by the runtime at the start of the first kernel and
+// the end of the last kernel of one step launch (hipExtLaunchKernelGGL), so
+// that their elapsed time is the kernels' own execution time.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+// Launchers (fdw_iso.hip, fdw_tti.hip, fdw_sparse.hip).  Each returns the
+// hipError_t of its launch.
+hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream_t s, const LaunchEvents &ev);
+hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s, const LaunchEvents &ev);
 hipError_t launch_inject(const SparseArgs &a, hipStream_t s);
 hipError_t launch_interp(const SparseArgs &a, hipStream_t s);
-hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s);
+hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s, const LaunchEvents &ev);
 hipError_t launch_zero_halo(int ndim, const Geom &g, int R, int64_t pitch_x, int64_t pitch_y,
                             int64_t planes, float *base, hipStream_t s);
 

@@ -191,14 +191,11 @@ __global__ void __launch_bounds__(1024) iso2d_persistent(Persist2DArgs a) {
 // ---------------------------------------------------------------------------
 
 template <int NDIM, int R>
-static hipError_t launch_iso_naive(const IsoArgs &a, hipStream_t s) {
-    if (NDIM == 3) {
-        dim3 blk(64, 4, 1), grd((a.g.nx + 63) / 64, (a.g.ny + 3) / 4, a.g.nz);
-        hipLaunchKernelGGL((iso_naive<NDIM, R>), grd, blk, 0, s, a);
-    } else {
-        dim3 blk(64, 4, 1), grd((a.g.nx + 63) / 64, (a.g.nz + 3) / 4, 1);
-        hipLaunchKernelGGL((iso_naive<NDIM, R>), grd, blk, 0, s, a);
-    }
+static hipError_t launch_iso_naive(const IsoArgs &a, hipStream_t s, const LaunchEvents &ev) {
+    dim3 blk(64, 4, 1);
+    dim3 grd = NDIM == 3 ? dim3((a.g.nx + 63) / 64, (a.g.ny + 3) / 4, a.g.nz)
+                         : dim3((a.g.nx + 63) / 64, (a.g.nz + 3) / 4, 1);
+    hipExtLaunchKernelGGL((iso_naive<NDIM, R>), grd, blk, 0, s, ev.start, ev.stop, 0, a);
     return hipGetLastError();
 }
 
@@ -222,7 +219,7 @@ static IsoShape iso_stream_shape(const Geom &g) {
 }
 
 template <int R, int NY, int PF, int BY>
-static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t s) {
+static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t s, const LaunchEvents &ev) {
     IsoOp op;
     op.c = a.c;
     op.eta = DampTables{a.eta_x, a.eta_y, a.eta_z};
@@ -235,41 +232,41 @@ static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t 
     F.p[1] = a.m;
     F.pout[0] = 0.0f;
     F.pout[1] = 1.0f;
-    return launch_stream3d<R, NY, PF, BY>(op, F, a.g, zc, s);
+    return launch_stream3d<R, NY, PF, BY>(op, F, a.g, zc, s, ev.start, ev.stop);
 }
 
 template <int R, int NY, int PF>
-static hipError_t launch_iso3d_stream_by(const IsoArgs &a, const IsoShape &sh, hipStream_t s) {
-    if (sh.by == 8) return launch_iso3d_stream_cfg<R, NY, PF, 8>(a, sh.zc, s);
-    return launch_iso3d_stream_cfg<R, NY, PF, 4>(a, sh.zc, s);
+static hipError_t launch_iso3d_stream_by(const IsoArgs &a, const IsoShape &sh, hipStream_t s, const LaunchEvents &ev) {
+    if (sh.by == 8) return launch_iso3d_stream_cfg<R, NY, PF, 8>(a, sh.zc, s, ev);
+    return launch_iso3d_stream_cfg<R, NY, PF, 4>(a, sh.zc, s, ev);
 }
 
 template <int R, int NY>
-static hipError_t launch_iso3d_stream_ny(const IsoArgs &a, const IsoShape &sh, hipStream_t s) {
-    if (sh.pf == 2) return launch_iso3d_stream_by<R, NY, 2>(a, sh, s);
-    return launch_iso3d_stream_by<R, NY, 1>(a, sh, s);
+static hipError_t launch_iso3d_stream_ny(const IsoArgs &a, const IsoShape &sh, hipStream_t s, const LaunchEvents &ev) {
+    if (sh.pf == 2) return launch_iso3d_stream_by<R, NY, 2>(a, sh, s, ev);
+    return launch_iso3d_stream_by<R, NY, 1>(a, sh, s, ev);
 }
 
 // Tuning variants are instantiated for R = 4 (space order 8) only; other
 // orders use the default shape.
 template <int R>
-static hipError_t launch_iso3d_stream(const IsoArgs &a, hipStream_t s) {
+static hipError_t launch_iso3d_stream(const IsoArgs &a, hipStream_t s, const LaunchEvents &ev) {
     const IsoShape sh = iso_stream_shape(a.g);
     if constexpr (R == 4) {
-        if (sh.ny == 1) return launch_iso3d_stream_ny<R, 1>(a, sh, s);
-        if (sh.ny == 2) return launch_iso3d_stream_ny<R, 2>(a, sh, s);
-        return launch_iso3d_stream_ny<R, 4>(a, sh, s);
+        if (sh.ny == 1) return launch_iso3d_stream_ny<R, 1>(a, sh, s, ev);
+        if (sh.ny == 2) return launch_iso3d_stream_ny<R, 2>(a, sh, s, ev);
+        return launch_iso3d_stream_ny<R, 4>(a, sh, s, ev);
     } else {
-        return launch_iso3d_stream_cfg<R, 4, 1, 4>(a, sh.zc, s);
+        return launch_iso3d_stream_cfg<R, 4, 1, 4>(a, sh.zc, s, ev);
     }
 }
 
-hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream_t s) {
-#define ISO_S3(r) launch_iso3d_stream<r>(a, s)
+hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream_t s, const LaunchEvents &ev) {
+#define ISO_S3(r) launch_iso3d_stream<r>(a, s, ev)
     if (ndim == 3 && v == IsoVariant::Stream) { FDW_DISPATCH_R(R, ISO_S3) }
 #undef ISO_S3
-#define ISO_N3(r) launch_iso_naive<3, r>(a, s)
-#define ISO_N2(r) launch_iso_naive<2, r>(a, s)
+#define ISO_N3(r) launch_iso_naive<3, r>(a, s, ev)
+#define ISO_N2(r) launch_iso_naive<2, r>(a, s, ev)
     if (ndim == 3) { FDW_DISPATCH_R(R, ISO_N3) }
     FDW_DISPATCH_R(R, ISO_N2)
 #undef ISO_N3
@@ -277,14 +274,15 @@ hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream
 }
 
 template <int R, bool HALO>
-static hipError_t launch_iso2d_persistent_h(const Persist2DArgs &a, size_t lds, hipStream_t s) {
+static hipError_t launch_iso2d_persistent_h(const Persist2DArgs &a, size_t lds, hipStream_t s, const LaunchEvents &ev) {
     const int ppt = (a.g.nx * a.g.nz + 1023) / 1024;
 #define P2D(PPT_)                                                                                       \
     {                                                                                                   \
         hipError_t e = hipFuncSetAttribute((const void *)iso2d_persistent<R, PPT_, HALO>,              \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
         if (e != hipSuccess) return e;                                                                  \
-        hipLaunchKernelGGL((iso2d_persistent<R, PPT_, HALO>), dim3(1), dim3(1024), lds, s, a);         \
+        hipExtLaunchKernelGGL((iso2d_persistent<R, PPT_, HALO>), dim3(1), dim3(1024), lds, s, ev.start, \
+                              ev.stop, 0, a);                                                           \
         return hipGetLastError();                                                                       \
     }
     if (ppt <= 8) P2D(8)
@@ -296,15 +294,15 @@ static hipError_t launch_iso2d_persistent_h(const Persist2DArgs &a, size_t lds, 
 }
 
 template <int R>
-static hipError_t launch_iso2d_persistent_r(const Persist2DArgs &a, hipStream_t s) {
+static hipError_t launch_iso2d_persistent_r(const Persist2DArgs &a, hipStream_t s, const LaunchEvents &ev) {
     const size_t halo = sizeof(float) * (size_t)(a.g.nx + 2 * R) * (size_t)(a.g.nz + 2 * R);
-    if (halo <= (size_t)kPersist2DMaxLds) return launch_iso2d_persistent_h<R, true>(a, halo, s);
-    return launch_iso2d_persistent_h<R, false>(a, sizeof(float) * (size_t)a.g.nx * a.g.nz, s);
+    if (halo <= (size_t)kPersist2DMaxLds) return launch_iso2d_persistent_h<R, true>(a, halo, s, ev);
+    return launch_iso2d_persistent_h<R, false>(a, sizeof(float) * (size_t)a.g.nx * a.g.nz, s, ev);
 }
 
-hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s) {
+hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s, const LaunchEvents &ev) {
     if ((size_t)a.g.nx * a.g.nz * sizeof(float) > (size_t)kPersist2DMaxLds) return hipErrorInvalidValue;
-#define P2R(r) launch_iso2d_persistent_r<r>(a, s)
+#define P2R(r) launch_iso2d_persistent_r<r>(a, s, ev)
     FDW_DISPATCH_R(R, P2R)
 #undef P2R
 }

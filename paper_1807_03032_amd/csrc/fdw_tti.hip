@@ -186,14 +186,14 @@ struct TtiS2Op {
 // ---------------------------------------------------------------------------
 
 template <int NDIM, int R>
-static hipError_t launch_tti_naive(const TtiArgs &a, hipStream_t s) {
+static hipError_t launch_tti_naive(const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {
     dim3 blk(64, 4, 1);
     dim3 grd = NDIM == 3 ? dim3((a.g.nx + 63) / 64, (a.g.ny + 3) / 4, a.g.nz)
                          : dim3((a.g.nx + 63) / 64, (a.g.nz + 3) / 4, 1);
-    hipLaunchKernelGGL((tti_naive_stage1<NDIM, R>), grd, blk, 0, s, a);
+    hipExtLaunchKernelGGL((tti_naive_stage1<NDIM, R>), grd, blk, 0, s, ev.start, nullptr, 0, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((tti_naive_stage2<NDIM, R>), grd, blk, 0, s, a);
+    hipExtLaunchKernelGGL((tti_naive_stage2<NDIM, R>), grd, blk, 0, s, nullptr, ev.stop, 0, a);
     return hipGetLastError();
 }
 
@@ -214,27 +214,30 @@ static TtiShape tti_stream_shape(const Geom &g) {
 }
 
 template <int R, int NY, int BY, class Op, int NQ, int NP>
-static hipError_t launch_tti_stage(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s) {
-    return launch_stream3d<R, NY, 1, BY>(op, F, g, zc, s);
+static hipError_t launch_tti_stage(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s,
+                                   hipEvent_t e0, hipEvent_t e1) {
+    return launch_stream3d<R, NY, 1, BY>(op, F, g, zc, s, e0, e1);
 }
 
 // Tuning variants are instantiated for R = 6 (space order 12) only; other
 // orders use (NY, BY) = (2, 8) for stage 1 and (1, 8) for stage 2.
 template <int R, class Op, int NQ, int NP>
 static hipError_t launch_tti_stage_shape(int ny, int by, const Op &op, const StreamFields<NQ, NP> &F, const Geom &g,
-                                         int zc, hipStream_t s) {
+                                         int zc, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if constexpr (R == 6) {
         if (ny == 2)
-            return by == 8 ? launch_tti_stage<R, 2, 8>(op, F, g, zc, s) : launch_tti_stage<R, 2, 4>(op, F, g, zc, s);
-        return by == 8 ? launch_tti_stage<R, 1, 8>(op, F, g, zc, s) : launch_tti_stage<R, 1, 4>(op, F, g, zc, s);
+            return by == 8 ? launch_tti_stage<R, 2, 8>(op, F, g, zc, s, e0, e1)
+                           : launch_tti_stage<R, 2, 4>(op, F, g, zc, s, e0, e1);
+        return by == 8 ? launch_tti_stage<R, 1, 8>(op, F, g, zc, s, e0, e1)
+                       : launch_tti_stage<R, 1, 4>(op, F, g, zc, s, e0, e1);
     } else {
-        if (NQ == 2) return launch_tti_stage<R, 2, 8>(op, F, g, zc, s);
-        return launch_tti_stage<R, 1, 8>(op, F, g, zc, s);
+        if (NQ == 2) return launch_tti_stage<R, 2, 8>(op, F, g, zc, s, e0, e1);
+        return launch_tti_stage<R, 1, 8>(op, F, g, zc, s, e0, e1);
     }
 }
 
 template <int R>
-static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s) {
+static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {
     const TtiShape sh = tti_stream_shape(a.g);
     TtiS1Op o1;
     o1.c = a.c;
@@ -246,7 +249,7 @@ static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s) {
     F1.p[0] = a.theta;
     F1.p[1] = a.phi;
     F1.pout[0] = F1.pout[1] = 0.0f;
-    hipError_t e = launch_tti_stage_shape<R>(sh.ny1, sh.by1, o1, F1, a.g, sh.zc, s);
+    hipError_t e = launch_tti_stage_shape<R>(sh.ny1, sh.by1, o1, F1, a.g, sh.zc, s, ev.start, nullptr);
     if (e != hipSuccess) return e;
     TtiS2Op o2;
     o2.c = a.c;
@@ -265,15 +268,15 @@ static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s) {
         F2.pout[i] = 0.0f;
     }
     F2.pout[3] = 1.0f;  // m
-    return launch_tti_stage_shape<R>(sh.ny2, sh.by2, o2, F2, a.g, sh.zc, s);
+    return launch_tti_stage_shape<R>(sh.ny2, sh.by2, o2, F2, a.g, sh.zc, s, nullptr, ev.stop);
 }
 
-hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s) {
-#define TTI_S3(r) launch_tti3d_stream<r>(a, s)
+hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {
+#define TTI_S3(r) launch_tti3d_stream<r>(a, s, ev)
     if (ndim == 3 && v == TtiVariant::Stream) { FDW_DISPATCH_R(R, TTI_S3) }
 #undef TTI_S3
-#define TTI_N3(r) launch_tti_naive<3, r>(a, s)
-#define TTI_N2(r) launch_tti_naive<2, r>(a, s)
+#define TTI_N3(r) launch_tti_naive<3, r>(a, s, ev)
+#define TTI_N2(r) launch_tti_naive<2, r>(a, s, ev)
     if (ndim == 3) { FDW_DISPATCH_R(R, TTI_N3) }
     FDW_DISPATCH_R(R, TTI_N2)
 #undef TTI_N3
