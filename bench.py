@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps of the bounded CPU sample")
     ap.add_argument("--tti", action="store_true", help="also time the 512^3 TTI so=12 operator")
+    ap.add_argument("--nslots", type=int, default=2, choices=(2, 3),
+                    help="wavefield storage of the isotropic workload: 2 = in-place leapfrog (default), "
+                         "3 = modulo-3 buffer u[t %% 3]")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -43,13 +46,13 @@ def parse():
     return ap.parse_args()
 
 
-def time_shot(prob, steps, warmup, device):
+def time_shot(prob, steps, warmup, device, nslots=3):
     """Warm up, reset to the zero initial state, then time `steps` time steps."""
     import torch
 
     from paper_1807_03032_amd import fdw
 
-    shot = fdw.Shot(prob, device)
+    shot = fdw.Shot(prob, device, nslots=nslots)
     stream = torch.cuda.current_stream(device)
     if warmup > 0:
         shot.apply(0, min(warmup, prob.nt) - 1)
@@ -248,7 +251,8 @@ def main():
         calib_copy(dev)
     prob = W.config_3d_iso_256(nt=max(1000, args.steps) if args.steps > 1000 else 1000)
     steps, warmup = args.steps, args.warmup
-    wall, kms, launches, desc, alg_bytes, tr, f = time_shot(prob, steps, warmup, dev)
+    wall, kms, launches, desc, alg_bytes, tr, f = time_shot(prob, steps, warmup, dev, args.nslots)
+    desc = f"{desc} slots={args.nslots}"
     value = prob.npoints * steps / wall / 1e9
     line = {
         "metric": "GPts/s (iso so=8, FP32)",
@@ -265,7 +269,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "3D isotropic acoustic 256^3, h=10 m, v 1500/2500 m/s two-layer, so=8, nbl=40, "
                                "15 Hz Ricker source, 256x256 receiver plane (trilinear), 1000 steps",
-                   "grid": list(prob.shape), "space_order": prob.so, "nt": prob.nt, "kernel": desc},
+                   "grid": list(prob.shape), "space_order": prob.so, "nt": prob.nt, "kernel": desc,
+                   "wavefield_storage": "in-place leapfrog, 2 slots" if args.nslots == 2 else "modulo-3 buffer"},
         "roofline": roofline(prob, kms, launches, alg_bytes, load_traffic("iso", desc)),
     }
     ops_seen = [{"desc": desc, "source_hash": source_hash("iso"), "kernel_match": ["IsoOp", "iso_naive"]}]

@@ -68,8 +68,10 @@ typedef struct fdw_op fdw_op;
  *   3D element (x, y, z) at  origin_offset + (z * pitch_y + y) * pitch_x + x
  *   2D element (x, z)    at  origin_offset +  z * pitch_x + x
  * A field occupies elems_per_slot floats; a TimeFunction with time_order 2
- * holds 3 slots back to back, logical time level t in slot t mod 3 (Section
- * 3.5: u[t % 3]; level -1 lives in slot 2). */
+ * holds nslots = 3 slots back to back, logical time level t in slot t mod 3
+ * (Section 3.5: u[t % 3]; level -1 lives in slot 2), or nslots = 2 slots with
+ * level t in slot t mod 2 (in-place leapfrog storage, see
+ * fdw_timefunction_bind). */
 typedef struct {
     int ndim;              /* 2 or 3                                              */
     int halo;              /* R = space_order / 2                                 */
@@ -126,14 +128,20 @@ int fdw_function_bind(fdw_grid *grid, const char *name, float *dptr, int64_t nel
                       fdw_func **out);
 int fdw_function_destroy(fdw_func *f);
 
-/* TimeFunction (Section 3.1, 3.5): a wavefield with time_order + 1 slots
- * (time_order must be 2: 3 slots), level t in slot t mod 3.  dptr holds
- * nelem >= 3 * elems_per_slot floats, 256-byte aligned.  The caller writes the
- * initial levels -1 and 0 (zeros give the zero initial conditions of eq. WE).
- * fdw_operator_create zeroes the halo of every slot; the library never writes
- * it afterwards.  Errors: FDW_ERR_ARG, FDW_ERR_LAYOUT. */
+/* TimeFunction (Section 3.1, 3.5): a wavefield of time order 2 (time_order
+ * must be 2) stored in nslots slots, level t in slot t mod nslots:
+ *   nslots = 3: the paper's modulo buffer u[t % 3] (time_order + 1 slots);
+ *   nslots = 2: in-place leapfrog storage -- step t overwrites level t-1 with
+ *               level t+1 point by point (each point's u(t-1) is read only by
+ *               the update of that point), one third less memory and per-step
+ *               working set; after an apply the slots hold the last two levels.
+ * dptr holds nelem >= nslots * elems_per_slot floats, 256-byte aligned.  The
+ * caller writes the initial levels -1 and 0 (zeros give the zero initial
+ * conditions of eq. WE).  fdw_operator_create zeroes the halo of every slot;
+ * the library never writes it afterwards.
+ * Errors: FDW_ERR_ARG (time_order, nslots), FDW_ERR_LAYOUT. */
 int fdw_timefunction_bind(fdw_grid *grid, const char *name, float *dptr, int64_t nelem,
-                          int space_order, int time_order, fdw_tfunc **out);
+                          int space_order, int time_order, int nslots, fdw_tfunc **out);
 int fdw_timefunction_destroy(fdw_tfunc *f);
 
 /* SparseTimeFunction (Section 3.3, eq. interp, Listing finject).

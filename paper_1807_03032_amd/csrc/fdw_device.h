@@ -10,6 +10,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 namespace fdw {
 
@@ -19,6 +20,15 @@ namespace fdw {
 
 // 1/m with the hardware reciprocal (1 ulp); m = 1/v^2 is a normal float.
 __device__ __forceinline__ float fast_rcp(float m) { return __builtin_amdgcn_rcpf(m); }
+
+// Workgroup barrier that orders LDS only: waits for this wave's LDS accesses
+// (lgkmcnt), not for its global loads, so loads issued for later planes stay
+// in flight across the barrier.  (__syncthreads also drains vmcnt.)
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Leapfrog update with the damping term (centred first time derivative):
 //   u+ = [2u - (1 - a) u- + c L] / (1 + a),   a = eta dt / 2,  c = dt^2 / m.
@@ -124,10 +134,11 @@ struct PlaneLoads {
     float pw[NP][NY];    // pointwise fields at z
     float hy[NQ][NHY];   // y-halo rows at z
     float hx[NQ][NHX];   // x-halo elements at z
+    float pv;            // the operator's per-plane value at z
 };
 
 // What an operator sees for one output point.
-template <int R, int NQ, int NP, int NY, int LH, int LW>
+template <int R, int NQ, int NP, int NY, int LH, int LW, int DIR>
 struct StreamPoint {
     const float (&q)[NQ][NY][2 * R + 1];
     const float (&lds)[NQ][LH][LW];
@@ -136,14 +147,16 @@ struct StreamPoint {
     int x, y, z;          // grid coordinates
     uint32_t off;         // element offset of the point
     // field f at (x, y, z + k), (x + k, y, z), (x, y + k, z); k in [-R, R]
-    __device__ __forceinline__ float qz(int f, int k) const { return q[f][j][R + k]; }
+    // (queue entry R + i holds plane z + DIR * i)
+    __device__ __forceinline__ float qz(int f, int k) const { return q[f][j][R + DIR * k]; }
     __device__ __forceinline__ float qx(int f, int k) const { return lds[f][ly][lx + k]; }
     __device__ __forceinline__ float qy(int f, int k) const { return lds[f][ly + k][lx]; }
     __device__ __forceinline__ float p(int i) const { return pw[i][j]; }
 };
 
 template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
-__global__ void __launch_bounds__(64 * BY) stream3d(Op op, StreamFields<NQ, NP> F, Geom g, int zc, int ntx, int nty) {
+__global__ void __launch_bounds__(64 * BY) stream3d(Op op, StreamFields<NQ, NP> F, Geom g, int zc, int ntx, int nty,
+                                                   int zfast) {
     constexpr int NT = 64 * BY;  // threads per workgroup
     constexpr int TX = 64, TY = BY * NY, LW = TX + 2 * R, LH = TY + 2 * R, Q = 2 * R + 1;
     constexpr int NHY = (2 * R + BY - 1) / BY;       // y-halo rows per wavefront
@@ -151,10 +164,19 @@ __global__ void __launch_bounds__(64 * BY) stream3d(Op op, StreamFields<NQ, NP> 
     __shared__ float lds[2][NQ][LH][LW];
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
     int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int tx = tile % ntx;
-    tile /= ntx;
-    const int ty = tile % nty;
-    const int tz = tile / nty;
+    int tx, ty, tz;
+    if (zfast) {  // z-chunk fastest: every chunk of a column on one XCD
+        const int ntz = (g.nz + zc - 1) / zc;
+        tz = tile % ntz;
+        tile /= ntz;
+        tx = tile % ntx;
+        ty = tile / ntx;
+    } else {  // x fastest, then y, then z-chunk
+        tx = tile % ntx;
+        tile /= ntx;
+        ty = tile % nty;
+        tz = tile / nty;
+    }
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * zc;
     const int z1 = min(z0 + zc, g.nz);
     const int x = x0 + lane;
@@ -202,94 +224,111 @@ __global__ void __launch_bounds__(64 * BY) stream3d(Op op, StreamFields<NQ, NP> 
     const bool tile_flag = op.begin_tile(x0, TX, y0, TY, z0, z1);
 
     auto zin = [&](int z) { return z >= 0 && z < g.nz; };
-    auto issue = [&](PlaneLoads<NQ, NP, NY, NHY, NHX> &P, int z) {
-        const uint32_t zo = (uint32_t)z * sz;
-        const uint32_t zh = (uint32_t)(z + R) * sz;
-        const bool hin = zin(z + R);
-#pragma unroll
-        for (int f = 0; f < NQ; ++f) {
-#pragma unroll
-            for (int j = 0; j < NY; ++j) P.head[f][j] = (in[j] && hin) ? F.q[f][col0 + j * sy + zh] : 0.0f;
-#pragma unroll
-            for (int i = 0; i < NHY; ++i) P.hy[f][i] = hy_in[i] ? F.q[f][hy_col[i] + zo] : 0.0f;
-#pragma unroll
-            for (int i = 0; i < NHX; ++i) P.hx[f][i] = hx_in[i] ? F.q[f][hx_off[i] + zo] : 0.0f;
-        }
-#pragma unroll
-        for (int f = 0; f < NP; ++f)
-#pragma unroll
-            for (int j = 0; j < NY; ++j) P.pw[f][j] = in[j] ? F.p[f][col0 + j * sy + zo] : F.pout[f];
-    };
-
-    // warm-up: queues hold z0 - R .. z0 + R - 1
-    float q[NQ][NY][Q];
-#pragma unroll
-    for (int f = 0; f < NQ; ++f)
-#pragma unroll
-        for (int j = 0; j < NY; ++j)
-#pragma unroll
-            for (int k = 0; k < 2 * R; ++k) {
-                const int z = z0 - R + k;
-                q[f][j][k] = (in[j] && zin(z)) ? F.q[f][col0 + j * sy + (uint32_t)z * sz] : 0.0f;
-            }
-    PlaneLoads<NQ, NP, NY, NHY, NHX> P[PF];
-#pragma unroll
-    for (int s = 0; s < PF; ++s)
-        if (z0 + s < z1) issue(P[s], z0 + s);
-
-    int buf = 0;
-    for (int zb = z0; zb < z1; zb += PF) {
-#pragma unroll
-        for (int s = 0; s < PF; ++s) {
-            const int z = zb + s;
-            if (z >= z1) break;
-            float cpw[NP][NY], chy[NQ][NHY], chx[NQ][NHX];
+    // Chunks alternate their walking direction along z (even chunk index: up,
+    // odd: down), so the two chunks that share a boundary read its warm-up
+    // planes at the same time -- both at their start or both at their end --
+    // and the second read can be served by the cache instead of HBM.  The
+    // queue entry R + i holds plane z + DIR * i.
+    auto run = [&](auto dir_tag) {
+        constexpr int DIR = decltype(dir_tag)::value;
+        const int nplanes = z1 - z0;
+        const int zs = DIR > 0 ? z0 : z1 - 1;  // first plane walked
+        auto issue = [&](PlaneLoads<NQ, NP, NY, NHY, NHX> &P, int z) {
+            const uint32_t zo = (uint32_t)z * sz;
+            const uint32_t zh = (uint32_t)(z + DIR * R) * sz;
+            const bool hin = zin(z + DIR * R);
 #pragma unroll
             for (int f = 0; f < NQ; ++f) {
 #pragma unroll
-                for (int j = 0; j < NY; ++j) q[f][j][2 * R] = P[s].head[f][j];
+                for (int j = 0; j < NY; ++j)
+                    P.head[f][j] = (in[j] && hin) ? F.q[f][col0 + j * sy + zh] : 0.0f;
 #pragma unroll
-                for (int i = 0; i < NHY; ++i) chy[f][i] = P[s].hy[f][i];
+                for (int i = 0; i < NHY; ++i) P.hy[f][i] = hy_in[i] ? F.q[f][hy_col[i] + zo] : 0.0f;
 #pragma unroll
-                for (int i = 0; i < NHX; ++i) chx[f][i] = P[s].hx[f][i];
+                for (int i = 0; i < NHX; ++i) P.hx[f][i] = hx_in[i] ? F.q[f][hx_off[i] + zo] : 0.0f;
             }
 #pragma unroll
             for (int f = 0; f < NP; ++f)
 #pragma unroll
-                for (int j = 0; j < NY; ++j) cpw[f][j] = P[s].pw[f][j];
-            if (z + PF < z1) issue(P[s], z + PF);
-            // plane z into LDS
+                for (int j = 0; j < NY; ++j) P.pw[f][j] = in[j] ? F.p[f][col0 + j * sy + zo] : F.pout[f];
+            P.pv = op.begin_plane(z);
+        };
+
+        // warm-up: queue entries 0 .. 2R-1 hold planes zs + DIR * (k - R)
+        float q[NQ][NY][Q];
 #pragma unroll
-            for (int f = 0; f < NQ; ++f) {
+        for (int f = 0; f < NQ; ++f)
 #pragma unroll
-                for (int j = 0; j < NY; ++j) lds[buf][f][R + wy * NY + j][R + lane] = q[f][j][R];
+            for (int j = 0; j < NY; ++j)
 #pragma unroll
-                for (int i = 0; i < NHY; ++i)
-                    if (hy_act[i]) lds[buf][f][hy_lds[i]][R + lane] = chy[f][i];
+                for (int k = 0; k < 2 * R; ++k) {
+                    const int z = zs + DIR * (k - R);
+                    q[f][j][k] = (in[j] && zin(z)) ? F.q[f][col0 + j * sy + (uint32_t)z * sz] : 0.0f;
+                }
+        PlaneLoads<NQ, NP, NY, NHY, NHX> P[PF];
 #pragma unroll
-                for (int i = 0; i < NHX; ++i)
-                    if (hx_act[i]) lds[buf][f][hx_lrow[i]][hx_lcol[i]] = chx[f][i];
+        for (int s = 0; s < PF; ++s)
+            if (s < nplanes) issue(P[s], zs + DIR * s);
+
+        int buf = 0;
+        for (int ib = 0; ib < nplanes; ib += PF) {
+#pragma unroll
+            for (int s = 0; s < PF; ++s) {
+                const int i = ib + s;
+                if (i >= nplanes) break;
+                const int z = zs + DIR * i;
+                float cpw[NP][NY], chy[NQ][NHY], chx[NQ][NHX];
+                const float plane_val = P[s].pv;
+#pragma unroll
+                for (int f = 0; f < NQ; ++f) {
+#pragma unroll
+                    for (int j = 0; j < NY; ++j) q[f][j][2 * R] = P[s].head[f][j];
+#pragma unroll
+                    for (int h = 0; h < NHY; ++h) chy[f][h] = P[s].hy[f][h];
+#pragma unroll
+                    for (int h = 0; h < NHX; ++h) chx[f][h] = P[s].hx[f][h];
+                }
+#pragma unroll
+                for (int f = 0; f < NP; ++f)
+#pragma unroll
+                    for (int j = 0; j < NY; ++j) cpw[f][j] = P[s].pw[f][j];
+                if (i + PF < nplanes) issue(P[s], z + DIR * PF);
+                // plane z into LDS
+#pragma unroll
+                for (int f = 0; f < NQ; ++f) {
+#pragma unroll
+                    for (int j = 0; j < NY; ++j) lds[buf][f][R + wy * NY + j][R + lane] = q[f][j][R];
+#pragma unroll
+                    for (int h = 0; h < NHY; ++h)
+                        if (hy_act[h]) lds[buf][f][hy_lds[h]][R + lane] = chy[f][h];
+#pragma unroll
+                    for (int h = 0; h < NHX; ++h)
+                        if (hx_act[h]) lds[buf][f][hx_lrow[h]][hx_lcol[h]] = chx[f][h];
+                }
+                lds_barrier();
+#pragma unroll
+                for (int j = 0; j < NY; ++j) {
+                    StreamPoint<R, NQ, NP, NY, LH, LW, DIR> pt{q, lds[buf], cpw, j, R + wy * NY + j, R + lane,
+                                                               x, yb + j, z, col0 + j * sy + (uint32_t)z * sz};
+                    // computed for every column (keeps the NY columns in one scheduling
+                    // region); only stores are predicated on the column being in the domain
+                    op.template point<R>(pt, tile_flag, colv[j] + plane_val, in[j]);
+                }
+                // advance the queues
+#pragma unroll
+                for (int f = 0; f < NQ; ++f)
+#pragma unroll
+                    for (int j = 0; j < NY; ++j)
+#pragma unroll
+                        for (int k = 0; k < 2 * R; ++k) q[f][j][k] = q[f][j][k + 1];
+                buf ^= 1;
             }
-            __syncthreads();
-            const float plane_val = op.begin_plane(z);
-#pragma unroll
-            for (int j = 0; j < NY; ++j) {
-                StreamPoint<R, NQ, NP, NY, LH, LW> pt{q, lds[buf], cpw, j, R + wy * NY + j, R + lane,
-                                                      x, yb + j, z, col0 + j * sy + (uint32_t)z * sz};
-                // computed for every column (keeps the NY columns in one scheduling
-                // region); only stores are predicated on the column being in the domain
-                op.template point<R>(pt, tile_flag, colv[j] + plane_val, in[j]);
-            }
-            // advance the queues
-#pragma unroll
-            for (int f = 0; f < NQ; ++f)
-#pragma unroll
-                for (int j = 0; j < NY; ++j)
-#pragma unroll
-                    for (int k = 0; k < 2 * R; ++k) q[f][j][k] = q[f][j][k + 1];
-            buf ^= 1;
         }
-    }
+    };
+    if (tz & 1)
+        run(std::integral_constant<int, -1>{});
+    else
+        run(std::integral_constant<int, 1>{});
 }
 
 // Does any fused source's interpolation cell touch the box
@@ -313,8 +352,11 @@ static hipError_t launch_stream3d(const Op &op, const StreamFields<NQ, NP> &F, c
                                   hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + BY * NY - 1) / (BY * NY), ntz = (g.nz + zc - 1) / zc;
     const int64_t nb = (int64_t)ntx * nty * ntz;
+    // tile order: FDW_TILE_ORDER=z puts the z-chunk index fastest (tuning knob)
+    const char *order = std::getenv("FDW_TILE_ORDER");
+    const int zfast = (order && order[0] == 'z') ? 1 : 0;
     hipExtLaunchKernelGGL((stream3d<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)nb), dim3(64 * BY), 0, s, e0, e1, 0, op,
-                          F, g, zc, ntx, nty);
+                          F, g, zc, ntx, nty, zfast);
     return hipGetLastError();
 }
 

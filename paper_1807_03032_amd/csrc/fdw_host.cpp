@@ -79,6 +79,7 @@ struct fdw_tfunc {
     int64_t nelem;
     int so;
     int time_order;
+    int nslots;  // 3: level t in slot t mod 3; 2: in-place leapfrog
     fdw_layout lay;
     int refs = 0;
 };
@@ -290,15 +291,16 @@ int fdw_function_destroy(fdw_func *f) {
 }
 
 int fdw_timefunction_bind(fdw_grid *grid, const char *name, float *dptr, int64_t nelem, int space_order,
-                          int time_order, fdw_tfunc **out) {
+                          int time_order, int nslots, fdw_tfunc **out) {
     FDW_GUARD_BEGIN
     if (!grid || !out) return fail(FDW_ERR_ARG, "timefunction_bind: NULL grid/out");
     if (!valid_so(space_order))
         return fail(FDW_ERR_ARG, "timefunction_bind: space_order %d not even in [2,16]", space_order);
     if (time_order != 2) return fail(FDW_ERR_ARG, "timefunction_bind: time_order must be 2 (got %d)", time_order);
+    if (nslots != 2 && nslots != 3) return fail(FDW_ERR_ARG, "timefunction_bind: nslots must be 2 or 3 (got %d)", nslots);
     fdw_layout L;
     compute_layout(grid, space_order, &L);
-    int st = check_buffer("timefunction_bind", dptr, nelem, 3 * L.elems_per_slot);
+    int st = check_buffer("timefunction_bind", dptr, nelem, (int64_t)nslots * L.elems_per_slot);
     if (st) return st;
     fdw_tfunc *f = new fdw_tfunc();
     f->grid = grid;
@@ -307,6 +309,7 @@ int fdw_timefunction_bind(fdw_grid *grid, const char *name, float *dptr, int64_t
     f->nelem = nelem;
     f->so = space_order;
     f->time_order = time_order;
+    f->nslots = nslots;
     f->lay = L;
     grid->refs++;
     *out = f;
@@ -466,6 +469,7 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
         if ((st = check_func("theta", d.theta, g, so))) return st;
         if (g->ndim == 3 && (st = check_func("phi", d.phi, g, so))) return st;
         if (d.r == d.u) return fail(FDW_ERR_ARG, "operator_create: p and r must be distinct TimeFunctions");
+        if (d.r->nslots != d.u->nslots) return fail(FDW_ERR_ARG, "operator_create: p and r must use the same slot count");
     } else if (d.r) {
         return fail(FDW_ERR_ARG, "operator_create: r must be NULL for the isotropic operator");
     }
@@ -598,7 +602,7 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
     std::vector<fdw_tfunc *> tfs{d.u};
     if (d.kind == FDW_TTI) tfs.push_back(d.r);
     for (fdw_tfunc *tf : tfs)
-        for (int sl = 0; sl < 3; ++sl) {
+        for (int sl = 0; sl < tf->nslots; ++sl) {
             e = launch_zero_halo(op->ndim, G, op->R, L.pitch_x, L.pitch_y, L.planes,
                                  tf->d + (int64_t)sl * L.elems_per_slot, nullptr);
             if (e != hipSuccess) break;
@@ -696,6 +700,7 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         pa.g = op->geom;
         pa.u = d.u->d;
         pa.slot = E;
+        pa.nslots = d.u->nslots;
         pa.pitch_x = L.pitch_x;
         pa.m = d.m->d;
         pa.eta_x = eta_x;
@@ -723,7 +728,9 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         return FDW_OK;
     }
     for (int t = time_m; t <= time_M; ++t) {
-        const int sc = t % 3, sp = (t + 2) % 3, sn = (t + 1) % 3;
+        // level k lives in slot k mod S; with S = 2 the new level overwrites t - 1
+        const int S = d.u->nslots;
+        const int sc = t % S, sp = (t + S - 1) % S, sn = (t + 1) % S;
         FusedSrc fs{};
         if (op->src_fused && nsrc > 0) {
             fs = op->fsrc_template;

@@ -81,8 +81,9 @@ struct SparseArgs {
 // a small 2D grid with the current level resident in LDS.
 struct Persist2DArgs {
     Geom g;
-    float *u;            // TimeFunction base (3 slots)
+    float *u;            // TimeFunction base (nslots slots)
     int64_t slot;        // elements per slot
+    int nslots;          // 3, or 2 for in-place storage
     int64_t pitch_x;     // row pitch of the padded layout
     const float *m;
     const float *eta_x, *eta_z;

@@ -76,8 +76,8 @@ struct IsoOp {
 //   3. barrier; source corners are added in LDS with LDS atomics;
 //   4. barrier; receivers are interpolated from LDS (4 corners, one thread
 //      each) and, in the last three steps, the level is written to its slot.
-// After the apply the three slots hold the same levels as with per-step
-// launches (levels time_M - 1, time_M, time_M + 1 in their slots).
+// After the apply the slots hold the same levels as with per-step launches
+// (the last nslots levels, each in its slot).
 // ---------------------------------------------------------------------------
 template <int R, int PPT, bool HALO>
 __global__ void __launch_bounds__(1024) iso2d_persistent(Persist2DArgs a) {
@@ -95,8 +95,9 @@ __global__ void __launch_bounds__(1024) iso2d_persistent(Persist2DArgs a) {
     auto goff = [&](int i) { return off0 + (int64_t)(i / nx) * px + (i % nx); };
     float prev[PPT], cdt[kCacheCoef ? PPT : 1], damp[kCacheCoef ? PPT : 1];
     {
-        const float *uc = a.u + (int64_t)(a.time_m % 3) * a.slot;
-        const float *up = a.u + (int64_t)((a.time_m + 2) % 3) * a.slot;
+        const int S = a.nslots;
+        const float *uc = a.u + (int64_t)(a.time_m % S) * a.slot;
+        const float *up = a.u + (int64_t)((a.time_m + S - 1) % S) * a.slot;
         if (HALO)
             for (int i = tid; i < (nz + 2 * R) * lw; i += 1024) lds_level[i] = 0.0f;
         __syncthreads();
@@ -165,8 +166,8 @@ __global__ void __launch_bounds__(1024) iso2d_persistent(Persist2DArgs a) {
             }
         }
         __syncthreads();
-        if (t >= a.time_M - 2) {
-            float *un = a.u + (int64_t)((t + 1) % 3) * a.slot;
+        if (t >= a.time_M - (a.nslots - 1)) {
+            float *un = a.u + (int64_t)((t + 1) % a.nslots) * a.slot;
             for (int i = tid; i < n; i += 1024) un[goff(i)] = cur[li(i)];
         }
         if (a.nrec > 0) {
@@ -207,7 +208,7 @@ struct IsoShape {
 };
 
 static IsoShape iso_stream_shape(const Geom &g) {
-    IsoShape sh{4, 16, 1, 4};
+    IsoShape sh{2, 32, 2, 4};
     if (const char *e = std::getenv("FDW_ISO_TILE")) {
         int a = 0, b = 0, c = 1, d = 4;
         const int n = std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d);
@@ -257,7 +258,7 @@ static hipError_t launch_iso3d_stream(const IsoArgs &a, hipStream_t s, const Lau
         if (sh.ny == 2) return launch_iso3d_stream_ny<R, 2>(a, sh, s, ev);
         return launch_iso3d_stream_ny<R, 4>(a, sh, s, ev);
     } else {
-        return launch_iso3d_stream_cfg<R, 4, 1, 4>(a, sh.zc, s, ev);
+        return launch_iso3d_stream_cfg<R, 2, 2, 4>(a, sh.zc, s, ev);
     }
 }
 

@@ -202,7 +202,7 @@ struct TtiShape {
 };
 
 static TtiShape tti_stream_shape(const Geom &g) {
-    TtiShape sh{2, 8, 1, 8, 32};
+    TtiShape sh{2, 8, 1, 8, 64};
     if (const char *e = std::getenv("FDW_TTI_TILE")) {
         int a = 0, b = 0, c = 0, d = 0, z = 0;
         if (std::sscanf(e, "%d,%d,%d,%d,%d", &a, &b, &c, &d, &z) == 5 && (a == 1 || a == 2) && (b == 4 || b == 8) &&

@@ -83,7 +83,7 @@ def load(path: str = LIB_PATH):
         "fdw_field_layout": (i32, [vp, i32, ctypes.POINTER(fdw_layout)]),
         "fdw_function_bind": (i32, [vp, ctypes.c_char_p, vp, i64, i32, pvp]),
         "fdw_function_destroy": (i32, [vp]),
-        "fdw_timefunction_bind": (i32, [vp, ctypes.c_char_p, vp, i64, i32, i32, pvp]),
+        "fdw_timefunction_bind": (i32, [vp, ctypes.c_char_p, vp, i64, i32, i32, i32, pvp]),
         "fdw_timefunction_destroy": (i32, [vp]),
         "fdw_sparse_bind": (i32, [vp, ctypes.c_char_p, i32, i32, ctypes.POINTER(dbl), vp, pvp]),
         "fdw_sparse_destroy": (i32, [vp]),
@@ -153,9 +153,10 @@ def fdw_function_destroy(f):
     _chk(load().fdw_function_destroy(f))
 
 
-def fdw_timefunction_bind(g, name: str, dptr: int, nelem: int, space_order: int, time_order: int = 2) -> int:
+def fdw_timefunction_bind(g, name: str, dptr: int, nelem: int, space_order: int, time_order: int = 2,
+                          nslots: int = 3) -> int:
     out = ctypes.c_void_p()
-    _chk(load().fdw_timefunction_bind(g, name.encode(), dptr, nelem, space_order, time_order,
+    _chk(load().fdw_timefunction_bind(g, name.encode(), dptr, nelem, space_order, time_order, nslots,
                                       ctypes.byref(out)))
     return out.value
 
@@ -257,7 +258,7 @@ class Shot:
     current torch stream; `fields()` / `traces()` fetch results.
     """
 
-    def __init__(self, prob, device="cuda:0", u_init=None):
+    def __init__(self, prob, device="cuda:0", u_init=None, nslots: int = 3):
         import torch
 
         self.prob = prob
@@ -271,13 +272,14 @@ class Shot:
         self.wave = {}
         names = ["u"] if kind == FDW_ISO else ["p", "r"]
         self.tf = {}
+        self.nslots = nslots
         for nm in names:
-            t = alloc_field(self.lay, 3, self.device)
+            t = alloc_field(self.lay, nslots, self.device)
             self.wave[nm] = t
-            self.tf[nm] = fdw_timefunction_bind(self.grid, nm, t.data_ptr(), t.numel(), prob.so)
+            self.tf[nm] = fdw_timefunction_bind(self.grid, nm, t.data_ptr(), t.numel(), prob.so, 2, nslots)
         if u_init:
             for nm, (prev, cur) in u_init.items():
-                upload(self.wave[nm], self.lay, 2, prev)
+                upload(self.wave[nm], self.lay, nslots - 1, prev)  # level -1
                 upload(self.wave[nm], self.lay, 0, cur)
         self.par = {}
         self.fn = {}
@@ -329,7 +331,8 @@ class Shot:
         torch.cuda.synchronize(self.device)
         out = {}
         for nm, t in self.wave.items():
-            out[nm] = (download(t, self.lay, t_last % 3), download(t, self.lay, (t_last + 1) % 3))
+            S = self.nslots
+            out[nm] = (download(t, self.lay, t_last % S), download(t, self.lay, (t_last + 1) % S))
         return out
 
     def traces(self) -> np.ndarray:

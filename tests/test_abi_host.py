@@ -107,6 +107,14 @@ def test_bind_validation_without_device():
     with pytest.raises(fdw.FdwError) as e:
         fdw.fdw_timefunction_bind(g, "u", fake, 3 * lay.elems_per_slot, 8, time_order=1)
     assert e.value.code == fdw.FDW_ERR_ARG
+    with pytest.raises(fdw.FdwError) as e:
+        fdw.fdw_timefunction_bind(g, "u", fake, 4 * lay.elems_per_slot, 8, nslots=4)
+    assert e.value.code == fdw.FDW_ERR_ARG
+    with pytest.raises(fdw.FdwError) as e:
+        fdw.fdw_timefunction_bind(g, "u", fake, 2 * lay.elems_per_slot - 1, 8, nslots=2)
+    assert e.value.code == fdw.FDW_ERR_LAYOUT
+    t2 = fdw.fdw_timefunction_bind(g, "u", fake, 2 * lay.elems_per_slot, 8, nslots=2)
+    fdw.fdw_timefunction_destroy(t2)
     f = fdw.fdw_function_bind(g, "m", fake, lay.elems_per_slot, 8)
     with pytest.raises(fdw.FdwError) as e:
         fdw.fdw_grid_destroy(g)  # still referenced

@@ -40,9 +40,9 @@ def torch_dev():
     return torch.device("cuda:0")
 
 
-def gpu_run(prob, dev, splits=None, u_init=None, time_M=None):
+def gpu_run(prob, dev, splits=None, u_init=None, time_M=None, nslots=3):
     from paper_1807_03032_amd import fdw
-    shot = fdw.Shot(prob, dev, u_init=u_init)
+    shot = fdw.Shot(prob, dev, u_init=u_init, nslots=nslots)
     try:
         if splits:
             lo = 0
@@ -275,3 +275,28 @@ def test_one_thread_per_point_schedule(torch_dev, monkeypatch, kind, shape):
     assert "naive" in desc
     of, otr = oracle_run(prob)
     check(prob, gf, gtr, of, otr)
+
+
+@pytest.mark.parametrize("kind,shape,so", [("iso", (37, 29, 23), 8), ("tti", (33, 27, 21), 12), ("iso", (67, 45), 4),
+                                           ("iso", (401, 301), 4)])
+def test_inplace_two_slot_storage(torch_dev, kind, shape, so):
+    """Two-slot (in-place leapfrog) storage gives the oracle's results, and the
+    same bits as the three-slot modulo buffer."""
+    if len(shape) == 2 and shape[0] > 300:
+        src = np.array([[1200.0, 900.0]])
+        prob = W.small_problem(kind, shape, so, nt=30, seed=41, src_at=src, rec_coords=src + 20.0)
+    else:
+        prob = W.small_problem(kind, shape, so, nt=30, seed=41, nsrc=2, nrec=10)
+    say("two slots", kind, shape, so)
+    gf, gtr, _ = gpu_run(prob, torch_dev, nslots=2)
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+    gf3, gtr3, _ = gpu_run(prob, torch_dev, nslots=3)
+    for nm in gf:
+        np.testing.assert_array_equal(gf[nm][1], gf3[nm][1])
+        np.testing.assert_array_equal(gf[nm][0], gf3[nm][0])
+    np.testing.assert_array_equal(gtr, gtr3)
+    gfs, gtrs, _ = gpu_run(prob, torch_dev, nslots=2, splits=[4, 17])
+    for nm in gf:
+        np.testing.assert_array_equal(gf[nm][1], gfs[nm][1])
+    np.testing.assert_array_equal(gtr, gtrs)
