@@ -104,7 +104,21 @@ typedef struct {
     fdw_func *phi;       /* TTI 3D: azimuth angle (radians); NULL in 2D               */
     fdw_sparse *src;     /* sources, injected into u (p and r); may be NULL           */
     fdw_sparse *rec;     /* receivers, sampling u (p); may be NULL                    */
+    int mode;            /* FDW_FORWARD, or FDW_ADJOINT (isotropic only), see below   */
 } fdw_op_desc;
+
+/* Operator modes.  FDW_ADJOINT builds the transpose of the isotropic
+ * source-to-receiver map (the adjoint of Section 3.3's injection/interpolation
+ * pair, extended to the whole time loop): with nu = (dt^2/m) D^-1 lambda,
+ * D = 1 + eta dt/2, the transposed recurrence is the same leapfrog step run
+ * backwards in time.  An adjoint operator is the forward one with two changes:
+ * its sources' injected terms dt^2 w q / m are divided by D at each target
+ * point (they enter before the damping division), and its receivers sample
+ * D u.  To apply F^T to residual traces d[nt][nrec]: bind the receivers as
+ * the adjoint operator's src with data d reversed in time, the sources as its
+ * rec, run steps 0..nt-1, and reverse the recorded traces in time. */
+#define FDW_FORWARD 0
+#define FDW_ADJOINT 1
 
 /* Grid(shape, extent, origin), Section 3.1.  ndim in {2, 3}; shape[a] >= 2;
  * extent[a] > 0; spacing h_a = extent[a] / (shape[a] - 1).  origin may be
@@ -180,6 +194,24 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out);
  * are reported here, execution errors at the next call or fdw_sync.
  * Errors: FDW_ERR_ARG (range), FDW_ERR_DEVICE. */
 int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream);
+
+/* Subsampled level saving (Section 3.5, ConditionalDimension / save=): while
+ * the isotropic operator runs, every level L >= first_level with
+ * (L - first_level) % every == 0 and k = (L - first_level) / every < nlevels
+ * is also stored in buf + k * elems_per_slot (same layout; halos untouched).
+ * Level L is the one step L - 1 computes (after injection).  buf = NULL
+ * disables saving.  The store is fused into the stencil kernel when the sources
+ * are fused.  Errors: FDW_ERR_ARG (TTI operator, every < 1, nlevels < 0). */
+int fdw_operator_set_save(fdw_op *op, float *buf, int64_t nlevels, int every, int first_level);
+
+/* Adjoint-state gradient with respect to m (zero-lag imaging condition of the
+ * isotropic operator of `op`): for one step t,
+ *   grad += -nu [(u(t+1) - 2 u(t) + u(t-1)) / dt^2 + eta (u(t+1) - u(t-1)) / (2 dt)]
+ * over the domain, where nu is the adjoint wavefield level of that step.  All
+ * pointers are single slots in the operator's layout.  Enqueued on `stream`.
+ * Errors: FDW_ERR_ARG, FDW_ERR_DEVICE. */
+int fdw_gradient_accumulate(fdw_op *op, const float *nu, const float *u_next, const float *u_cur,
+                            const float *u_prev, float *grad, void *stream);
 
 /* Wait for all work the operator enqueued.  Errors: FDW_ERR_DEVICE. */
 int fdw_sync(fdw_op *op);

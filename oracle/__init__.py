@@ -261,3 +261,32 @@ def tti_run(grid: Grid, m, eps, delta, theta, phi, nt: int, p_prev=None, p_cur=N
                             _ptr(rec) if nr else None)
     _check(st, "tti_run")
     return pp, pc, rp, rcur, rec
+
+
+def iso_adjoint(grid: Grid, m, nt: int, src_coords, rec_coords, resid) -> np.ndarray:
+    """Transpose of the source-to-receiver map of iso_run (zero initial levels):
+    resid [nt][nrec] -> [nt][nsrc]."""
+    m = _field(grid, m)
+    sc, rc = _coords(grid, src_coords), _coords(grid, rec_coords)
+    d = np.ascontiguousarray(resid, dtype=np.float64)
+    assert d.shape == (nt, rc.shape[0])
+    out = np.zeros((nt, sc.shape[0]))
+    g = grid.c()
+    _check(_load().or_iso_adjoint(ctypes.byref(g), _ptr(m), ctypes.c_int(nt), ctypes.c_int(sc.shape[0]), _ptr(sc),
+                                  ctypes.c_int(rc.shape[0]), _ptr(rc), _ptr(d), _ptr(out)), "iso_adjoint")
+    return out
+
+
+def iso_gradient(grid: Grid, m, nt: int, src_coords, src, rec_coords, resid) -> np.ndarray:
+    """d/dm of sum_t <resid[t], rec[t]> for the forward run of iso_run."""
+    m = _field(grid, m)
+    sc, rc = _coords(grid, src_coords), _coords(grid, rec_coords)
+    q = np.ascontiguousarray(src, dtype=np.float64)
+    d = np.ascontiguousarray(resid, dtype=np.float64)
+    assert q.shape == (nt, sc.shape[0]) and d.shape == (nt, rc.shape[0])
+    out = np.zeros(grid.array_shape)
+    g = grid.c()
+    _check(_load().or_iso_gradient(ctypes.byref(g), _ptr(m), ctypes.c_int(nt), ctypes.c_int(sc.shape[0]), _ptr(sc),
+                                   _ptr(q), ctypes.c_int(rc.shape[0]), _ptr(rc), _ptr(d), _ptr(out)),
+           "iso_gradient")
+    return out

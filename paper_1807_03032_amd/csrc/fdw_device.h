@@ -58,17 +58,17 @@ __device__ __forceinline__ float laplacian_at(const float *u, int64_t i, const G
     return lap;
 }
 
-// Fused injection for the point (x, y, z): adds dt^2 w_c q_s / m for every
-// fused source s whose interpolation cell has this point as corner c.
+// Fused injection for the point (x, y, z): adds dt^2 w_c q_s / m (times scale)
+// for every fused source s whose interpolation cell has this point as corner c.
 __device__ __forceinline__ float fused_inject(const FusedSrc &src, int ndim, int x, int y, int z,
-                                              float rcp_m, float val) {
+                                              float rcp_m, float val, float scale = 1.0f) {
     for (int s = 0; s < src.n; ++s) {
         const unsigned dx = (unsigned)(x - src.bx[s]);
         const unsigned dy = (unsigned)(y - src.by[s]);
         const unsigned dz = (unsigned)(z - src.bz[s]);
         if (dx <= 1u && dy <= 1u && dz <= 1u) {
             const int c = ndim == 3 ? (int)(dx + 2u * dy + 4u * dz) : (int)(dx + 2u * dz);
-            val += src.w[s][c] * src.q[s] * rcp_m;
+            val += src.w[s][c] * src.q[s] * rcp_m * scale;
         }
     }
     return val;

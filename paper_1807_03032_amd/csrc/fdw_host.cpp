@@ -109,6 +109,11 @@ struct fdw_op {
     float *d_stage = nullptr;         // TTI: gp | gr (each elems_per_slot)
     int64_t *d_src_base = nullptr, *d_rec_base = nullptr;
     float *d_src_w = nullptr, *d_rec_w = nullptr;
+    int *d_src_idx = nullptr, *d_rec_idx = nullptr;  // [npoint][3] base grid indices
+    // subsampled level saving
+    float *save_buf = nullptr;
+    int64_t save_nlevels = 0;
+    int save_every = 1, save_first = 0;
     // host copies of the fused-source description
     FusedSrc fsrc_template;
     bool src_fused = false;
@@ -389,6 +394,9 @@ static void release_device(fdw_op *op) {
     if (op->d_rec_base) (void)hipFree(op->d_rec_base);
     if (op->d_src_w) (void)hipFree(op->d_src_w);
     if (op->d_rec_w) (void)hipFree(op->d_rec_w);
+    if (op->d_src_idx) (void)hipFree(op->d_src_idx);
+    if (op->d_rec_idx) (void)hipFree(op->d_rec_idx);
+    op->d_src_idx = op->d_rec_idx = nullptr;
     for (hipEvent_t e : op->ev_pool) (void)hipEventDestroy(e);
     op->ev_pool.clear();
     op->d_eta = op->d_stage = op->d_src_w = op->d_rec_w = nullptr;
@@ -401,11 +409,16 @@ static int64_t element_offset(const fdw_op *op, const int64_t *idx) {
     return op->geom.off0 + idx[1] * op->geom.sz + idx[0];
 }
 
-static int upload_sparse(fdw_op *op, const fdw_sparse *s, double scale, int64_t **d_base, float **d_w) {
+static int upload_sparse(fdw_op *op, const fdw_sparse *s, double scale, int64_t **d_base, float **d_w, int **d_idx) {
     const int nc = 1 << op->ndim;
     std::vector<int64_t> off(s->npoint);
     std::vector<float> w((size_t)s->npoint * nc);
+    std::vector<int> idx((size_t)std::max(1, s->npoint) * 3, 0);
     for (int p = 0; p < s->npoint; ++p) {
+        const int64_t *b = &s->base[(size_t)p * op->ndim];
+        idx[(size_t)p * 3 + 0] = (int)b[0];
+        idx[(size_t)p * 3 + 1] = op->ndim == 3 ? (int)b[1] : 0;
+        idx[(size_t)p * 3 + 2] = (int)b[op->ndim - 1];
         off[p] = element_offset(op, &s->base[(size_t)p * op->ndim]);
         for (int c = 0; c < nc; ++c) w[(size_t)p * nc + c] = (float)(scale * s->w[(size_t)p * nc + c]);
     }
@@ -413,9 +426,12 @@ static int upload_sparse(fdw_op *op, const fdw_sparse *s, double scale, int64_t 
     if (e != hipSuccess) return fail(FDW_ERR_NOMEM, "operator_create: hipMalloc sparse base: %s", hipGetErrorString(e));
     e = hipMalloc((void **)d_w, sizeof(float) * std::max<size_t>(1, w.size()));
     if (e != hipSuccess) return fail(FDW_ERR_NOMEM, "operator_create: hipMalloc sparse weights: %s", hipGetErrorString(e));
+    e = hipMalloc((void **)d_idx, sizeof(int) * idx.size());
+    if (e != hipSuccess) return fail(FDW_ERR_NOMEM, "operator_create: hipMalloc sparse indices: %s", hipGetErrorString(e));
     if (s->npoint > 0) {
         e = hipMemcpy(*d_base, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(*d_w, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(*d_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return fail_hip(e, "operator_create: sparse upload");
     }
     return FDW_OK;
@@ -443,7 +459,7 @@ static void pick_variants(fdw_op *op) {
     const bool naive = k && std::strcmp(k, "naive") == 0;
     op->iso_v = naive ? IsoVariant::Naive : IsoVariant::Stream;
     op->tti_v = naive ? TtiVariant::Naive : TtiVariant::Stream;
-    op->use_persist2d = !naive && op->d.kind == FDW_ISO && op->ndim == 2 &&
+    op->use_persist2d = !naive && op->d.kind == FDW_ISO && op->ndim == 2 && op->d.mode == FDW_FORWARD &&
                         (int64_t)op->geom.nx * op->geom.nz * (int64_t)sizeof(float) <= kPersist2DMaxLds;
 }
 
@@ -480,6 +496,9 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
     if (d.nbl < 0) return fail(FDW_ERR_ARG, "operator_create: nbl must be >= 0");
     const double rc = d.damp_rc == 0.0 ? 1e-3 : d.damp_rc;
     if (!(rc > 0.0 && rc < 1.0)) return fail(FDW_ERR_ARG, "operator_create: damp_rc must be in (0, 1)");
+    if (d.mode != FDW_FORWARD && d.mode != FDW_ADJOINT) return fail(FDW_ERR_ARG, "operator_create: unknown mode %d", d.mode);
+    if (d.mode == FDW_ADJOINT && d.kind != FDW_ISO)
+        return fail(FDW_ERR_ARG, "operator_create: the adjoint mode is available for the isotropic operator only");
     const double eps_max = d.kind == FDW_TTI ? d.eps_max : 0.0;
     if (!(eps_max >= 0.0)) return fail(FDW_ERR_ARG, "operator_create: eps_max must be >= 0");
     const double dtmax = stable_dt_axes(d.kind, g->ndim, so, d.vmax, eps_max, g->h);
@@ -563,7 +582,7 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
 
     // sparse preprocessing: element offsets and float weights
     if (d.src) {
-        st = upload_sparse(op, d.src, d.dt * d.dt, &op->d_src_base, &op->d_src_w);
+        st = upload_sparse(op, d.src, d.dt * d.dt, &op->d_src_base, &op->d_src_w, &op->d_src_idx);
         if (!st && d.src->npoint <= kMaxFusedSrc) {
             op->src_fused = true;
             FusedSrc &F = op->fsrc_template;
@@ -579,7 +598,7 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
             }
         }
     }
-    if (!st && d.rec) st = upload_sparse(op, d.rec, 1.0, &op->d_rec_base, &op->d_rec_w);
+    if (!st && d.rec) st = upload_sparse(op, d.rec, 1.0, &op->d_rec_base, &op->d_rec_w, &op->d_rec_idx);
     if (st) {
         release_device(op);
         delete op;
@@ -680,6 +699,12 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
     if (op->timing) op->last_stream = s;
 
     SparseArgs inj{};
+    inj.ndim = op->ndim;
+    inj.eta_x = eta_x;
+    inj.eta_y = eta_y;
+    inj.eta_z = eta_z;
+    inj.damp_mode = d.mode == FDW_ADJOINT ? 1 : 0;
+    inj.idx = op->d_src_idx;
     inj.npoint = nsrc;
     inj.ncorner = 1 << op->ndim;
     inj.base = op->d_src_base;
@@ -693,9 +718,11 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
     itp.base = op->d_rec_base;
     itp.w = op->d_rec_w;
     itp.m = nullptr;
+    itp.damp_mode = d.mode == FDW_ADJOINT ? 2 : 0;
+    itp.idx = op->d_rec_idx;
 
     // small 2D isotropic grids: the whole range in one persistent launch
-    if (d.kind == FDW_ISO && op->ndim == 2 && op->use_persist2d && time_M >= time_m) {
+    if (d.kind == FDW_ISO && op->ndim == 2 && op->use_persist2d && !op->save_buf && time_M >= time_m) {
         Persist2DArgs pa{};
         pa.g = op->geom;
         pa.u = d.u->d;
@@ -743,6 +770,7 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         }
         hipError_t e;
         float *next_field;
+        float *save_dst = nullptr;
         if (d.kind == FDW_ISO) {
             IsoArgs a{};
             a.g = op->geom;
@@ -756,6 +784,14 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             a.dt2 = op->dt2;
             a.c = op->coefs;
             a.src = fs;
+            a.adjoint = d.mode == FDW_ADJOINT;
+            a.save = nullptr;
+            const int L = t + 1;
+            if (op->save_buf && L >= op->save_first && (L - op->save_first) % op->save_every == 0 &&
+                (L - op->save_first) / op->save_every < op->save_nlevels) {
+                save_dst = op->save_buf + (int64_t)((L - op->save_first) / op->save_every) * E;
+                if (op->src_fused || nsrc == 0) a.save = save_dst;
+            }
             e = launch_iso(op->ndim, op->R, op->iso_v, a, s, ev);
             next_field = a.u_next;
         } else {
@@ -794,6 +830,10 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
                 if ((e = launch_inject(inj, s)) != hipSuccess) return fail_hip(e, "operator_apply: inject launch");
             }
         }
+        if (save_dst && !(op->src_fused || nsrc == 0)) {
+            e = hipMemcpyAsync(save_dst, next_field, sizeof(float) * (size_t)E, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return fail_hip(e, "operator_apply: save copy");
+        }
         if (nrec > 0) {
             itp.field = next_field;
             itp.rec_row = d.rec->data + (int64_t)t * nrec;
@@ -802,6 +842,37 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
     }
     return FDW_OK;
     FDW_GUARD_END
+}
+
+int fdw_operator_set_save(fdw_op *op, float *buf, int64_t nlevels, int every, int first_level) {
+    if (!op) return fail(FDW_ERR_ARG, "set_save: NULL op");
+    if (buf && op->d.kind != FDW_ISO) return fail(FDW_ERR_ARG, "set_save: level saving is available for the isotropic operator");
+    if (buf && (every < 1 || nlevels < 0)) return fail(FDW_ERR_ARG, "set_save: every must be >= 1 and nlevels >= 0");
+    op->save_buf = buf;
+    op->save_nlevels = buf ? nlevels : 0;
+    op->save_every = buf ? every : 1;
+    op->save_first = buf ? first_level : 0;
+    return FDW_OK;
+}
+
+int fdw_gradient_accumulate(fdw_op *op, const float *nu, const float *u_next, const float *u_cur,
+                            const float *u_prev, float *grad, void *stream) {
+    if (!op || !nu || !u_next || !u_cur || !u_prev || !grad) return fail(FDW_ERR_ARG, "gradient_accumulate: NULL argument");
+    if (op->d.kind != FDW_ISO) return fail(FDW_ERR_ARG, "gradient_accumulate: isotropic operators only");
+    GradArgs a{};
+    a.g = op->geom;
+    a.nu = nu;
+    a.u_next = u_next;
+    a.u_cur = u_cur;
+    a.u_prev = u_prev;
+    a.grad = grad;
+    a.eta_x = op->d_eta;
+    a.eta_y = op->d_eta + op->geom.nx;
+    a.eta_z = op->d_eta + op->geom.nx + op->geom.ny;
+    a.inv_dt2 = (float)(1.0 / (op->d.dt * op->d.dt));
+    hipError_t e = launch_gradient(op->ndim, a, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "gradient_accumulate: launch");
+    return FDW_OK;
 }
 
 int fdw_sync(fdw_op *op) {

@@ -51,6 +51,8 @@ struct IsoArgs {
     float dt2;
     Coefs c;
     FusedSrc src;
+    int adjoint;   // 1: injected terms are divided by the damping factor (1 + a)
+    float *save;   // optional: the new level is also stored here (same layout)
 };
 
 struct TtiArgs {
@@ -66,6 +68,12 @@ struct TtiArgs {
 };
 
 struct SparseArgs {
+    // adjoint mode: injection divides by (1 + a) and interpolation weights
+    // each corner by (1 + a), a = eta dt / 2 from the per-axis tables
+    int damp_mode;               // 0: none, 1: inject / (1 + a), 2: interp * (1 + a)
+    const int *idx;              // [npoint][3] base grid indices (x, y, z); y = 0 in 2D
+    const float *eta_x, *eta_y, *eta_z;
+    int ndim;
     int npoint;
     int ncorner;                 // 4 (2D) or 8 (3D)
     const int64_t *base;         // [npoint] element offset of corner 0
@@ -123,6 +131,15 @@ hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream
 hipError_t launch_inject(const SparseArgs &a, hipStream_t s);
 hipError_t launch_interp(const SparseArgs &a, hipStream_t s);
 hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s, const LaunchEvents &ev);
+// grad += -nu [(u+ - 2u + u-)/dt^2 + eta (u+ - u-)/(2 dt)] over the domain
+struct GradArgs {
+    Geom g;
+    const float *nu, *u_next, *u_cur, *u_prev;
+    float *grad;
+    const float *eta_x, *eta_y, *eta_z;  // damping a = eta dt / 2 per axis
+    float inv_dt2;                       // 1 / dt^2
+};
+hipError_t launch_gradient(int ndim, const GradArgs &a, hipStream_t s);
 hipError_t launch_zero_halo(int ndim, const Geom &g, int R, int64_t pitch_x, int64_t pitch_y,
                             int64_t planes, float *base, hipStream_t s);
 

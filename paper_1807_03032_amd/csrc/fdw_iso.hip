@@ -25,8 +25,9 @@ __global__ void __launch_bounds__(256) iso_naive(IsoArgs a) {
     const float rm = fast_rcp(a.m[i]);
     const float d = damp_at(a.eta_x, a.eta_y, a.eta_z, NDIM, x, y, z);
     float un = leapfrog(uc, a.u_prev[i], a.dt2 * rm * lap, d);
-    if (a.src.n) un = fused_inject(a.src, NDIM, x, y, z, rm, un);
+    if (a.src.n) un = fused_inject(a.src, NDIM, x, y, z, rm, un, a.adjoint ? 1.0f / (1.0f + d) : 1.0f);
     a.u_next[i] = un;
+    if (a.save) a.save[i] = un;
 }
 
 // ---- isotropic step: stencil field u(t); pointwise u(t-1), m ----------------
@@ -36,6 +37,8 @@ struct IsoOp {
     float dt2;
     FusedSrc src;
     float *u_next;
+    float *save;   // optional second destination of the new level
+    int adjoint;   // injected terms divided by (1 + a)
     // does a fused source touch this tile and chunk?
     __device__ __forceinline__ bool begin_tile(int x0, int tx, int y0, int ty, int z0, int z1) const {
         return src_in_tile(src, x0, tx, y0, ty, z0, z1);
@@ -58,8 +61,11 @@ struct IsoOp {
         }
         const float rm = fast_rcp(pt.p(1));
         float v = leapfrog(uc, pt.p(0), dt2 * rm * lap, a);
-        if (src_here) v = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, v);
-        if (live) u_next[pt.off] = v;
+        if (src_here) v = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, v, adjoint ? 1.0f / (1.0f + a) : 1.0f);
+        if (live) {
+            u_next[pt.off] = v;
+            if (save) save[pt.off] = v;
+        }
     }
 };
 
@@ -227,6 +233,8 @@ static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t 
     op.dt2 = a.dt2;
     op.src = a.src;
     op.u_next = a.u_next;
+    op.save = a.save;
+    op.adjoint = a.adjoint;
     StreamFields<1, 2> F;
     F.q[0] = a.u_cur;
     F.p[0] = a.u_prev;

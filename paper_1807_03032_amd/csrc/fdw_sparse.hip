@@ -16,12 +16,23 @@ __device__ __forceinline__ int64_t corner_offset(const SparseArgs &a, int c) {
     return ((c & 1) ? a.cstride[0] : 0) + ((c & 2) ? a.cstride[1] : 0) + ((c & 4) ? a.cstride[2] : 0);
 }
 
+// damping factor a = eta dt / 2 at corner c of sparse point p (adjoint modes)
+__device__ __forceinline__ float corner_damp(const SparseArgs &a, int p, int c) {
+    const int *b = a.idx + 3 * p;
+    const int x = b[0] + (c & 1);
+    if (a.ndim == 3) return a.eta_x[x] + a.eta_y[b[1] + ((c >> 1) & 1)] + a.eta_z[b[2] + ((c >> 2) & 1)];
+    return a.eta_x[x] + a.eta_z[b[2] + ((c >> 1) & 1)];
+}
+
 __global__ void __launch_bounds__(256) interp_kernel(SparseArgs a) {
     const int lane = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = lane / a.ncorner;
     const int c = lane % a.ncorner;
     float v = 0.0f;
-    if (p < a.npoint) v = a.w[(int64_t)p * a.ncorner + c] * a.field[a.base[p] + corner_offset(a, c)];
+    if (p < a.npoint) {
+        v = a.w[(int64_t)p * a.ncorner + c] * a.field[a.base[p] + corner_offset(a, c)];
+        if (a.damp_mode == 2) v *= 1.0f + corner_damp(a, p, c);
+    }
     // groups of 4 or 8 lanes are aligned inside the 64-wide wavefront
     v += __shfl_xor(v, 1);
     v += __shfl_xor(v, 2);
@@ -35,7 +46,26 @@ __global__ void __launch_bounds__(256) inject_kernel(SparseArgs a) {
     const int c = lane % a.ncorner;
     if (p >= a.npoint) return;
     const int64_t i = a.base[p] + corner_offset(a, c);
-    atomicAdd(a.field + i, a.w[(int64_t)p * a.ncorner + c] * a.q_row[p] * fast_rcp(a.m[i]));
+    float v = a.w[(int64_t)p * a.ncorner + c] * a.q_row[p] * fast_rcp(a.m[i]);
+    if (a.damp_mode == 1) v /= 1.0f + corner_damp(a, p, c);
+    atomicAdd(a.field + i, v);
+}
+
+// Imaging condition of the adjoint-state gradient with respect to m, one
+// thread per domain point:
+//   grad += -nu [(u+ - 2u + u-)/dt^2 + eta (u+ - u-)/(2 dt)],  eta dt/2 = a.
+template <int NDIM>
+__global__ void __launch_bounds__(256) gradient_kernel(GradArgs a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
+    const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+    const int64_t i = a.g.off0 + (int64_t)z * a.g.sz + (int64_t)y * a.g.sy + x;
+    const float damp = a.eta_x[x] + a.eta_z[z] + (NDIM == 3 ? a.eta_y[y] : 0.0f);
+    const float un = a.u_next[i], uc = a.u_cur[i], up = a.u_prev[i];
+    // (u+ - 2u + u-) + a (u+ - u-), divided by dt^2 (eta (u+ - u-)/(2 dt) = a (u+ - u-)/dt^2)
+    const float s = ((un - uc) - (uc - up)) + damp * (un - up);
+    a.grad[i] -= a.nu[i] * s * a.inv_dt2;
 }
 
 // Writes zero to every element of one slot outside the domain.
@@ -74,6 +104,18 @@ hipError_t launch_interp(const SparseArgs &a, hipStream_t s) {
     if (a.npoint <= 0) return hipSuccess;
     const int64_t lanes = (int64_t)a.npoint * a.ncorner;
     hipLaunchKernelGGL(interp_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gradient(int ndim, const GradArgs &a, hipStream_t s) {
+    dim3 blk(64, 4, 1);
+    if (ndim == 3) {
+        dim3 grd((a.g.nx + 63) / 64, (a.g.ny + 3) / 4, a.g.nz);
+        hipLaunchKernelGGL(gradient_kernel<3>, grd, blk, 0, s, a);
+    } else {
+        dim3 grd((a.g.nx + 63) / 64, (a.g.nz + 3) / 4, 1);
+        hipLaunchKernelGGL(gradient_kernel<2>, grd, blk, 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@ FDW_ERR_NOMEM = -6
 FDW_ERR_STATE = -7
 FDW_ISO = 0
 FDW_TTI = 1
+FDW_FORWARD = 0
+FDW_ADJOINT = 1
 FDW_X_OFFSET = 32
 
 # every symbol include/fdw.h declares
@@ -38,7 +40,7 @@ EXPORTS = (
     "fdw_timefunction_bind", "fdw_timefunction_destroy", "fdw_sparse_bind", "fdw_sparse_destroy",
     "fdw_operator_create", "fdw_operator_apply", "fdw_sync", "fdw_operator_destroy",
     "fdw_operator_set_timing", "fdw_operator_kernel_time", "fdw_operator_describe", "fdw_stable_dt",
-    "fdw_last_error", "fdw_version",
+    "fdw_last_error", "fdw_version", "fdw_operator_set_save", "fdw_gradient_accumulate",
 )
 
 
@@ -61,7 +63,7 @@ class fdw_op_desc(ctypes.Structure):
                 ("eps_max", ctypes.c_double), ("u", ctypes.c_void_p), ("r", ctypes.c_void_p),
                 ("m", ctypes.c_void_p), ("eps", ctypes.c_void_p), ("delta", ctypes.c_void_p),
                 ("theta", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("src", ctypes.c_void_p),
-                ("rec", ctypes.c_void_p)]
+                ("rec", ctypes.c_void_p), ("mode", ctypes.c_int)]
 
 
 _lib = None
@@ -95,6 +97,8 @@ def load(path: str = LIB_PATH):
         "fdw_operator_kernel_time": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
         "fdw_operator_describe": (i32, [vp, ctypes.c_char_p, i32, ctypes.POINTER(dbl)]),
         "fdw_stable_dt": (dbl, [i32, i32, i32, dbl, dbl, dbl]),
+        "fdw_operator_set_save": (i32, [vp, vp, i64, i32, i32]),
+        "fdw_gradient_accumulate": (i32, [vp, vp, vp, vp, vp, vp, vp]),
         "fdw_last_error": (ctypes.c_char_p, []),
         "fdw_version": (ctypes.c_char_p, []),
     }
@@ -194,6 +198,15 @@ def fdw_sync(op):
 
 def fdw_operator_destroy(op):
     _chk(load().fdw_operator_destroy(op))
+
+
+def fdw_operator_set_save(op, buf: Optional[int], nlevels: int = 0, every: int = 1, first_level: int = 0):
+    _chk(load().fdw_operator_set_save(op, buf, nlevels, every, first_level))
+
+
+def fdw_gradient_accumulate(op, nu: int, u_next: int, u_cur: int, u_prev: int, grad: int,
+                            stream: Optional[int] = None):
+    _chk(load().fdw_gradient_accumulate(op, nu, u_next, u_cur, u_prev, grad, stream))
 
 
 def fdw_operator_set_timing(op, enable: bool):

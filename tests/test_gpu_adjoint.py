@@ -1,0 +1,145 @@
+"""GPU adjoint and gradient (isotropic): parity with the oracle's transposed
+recurrence and gradient, the adjoint dot-product test in FP32, invariance of
+the gradient to the checkpoint interval, and a finite-difference check of the
+autograd wrapper."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_03032_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1807_03032_amd import fdw
+    fdw.load()
+    return torch.device("cuda:0")
+
+
+def problem(ndim, so, nt, seed, nrec=9):
+    shape = (34, 29, 25)[:ndim] if ndim == 3 else (70, 55)
+    prob = W.small_problem("iso", shape, so, nt=nt, seed=seed, nsrc=2, nrec=nrec, nbl=4)
+    return prob
+
+
+def model_for(prob, dev, K):
+    from paper_1807_03032_amd.modeling import IsoModeling
+    md = IsoModeling(prob.shape, prob.extent, prob.origin, prob.so, prob.dt, prob.nt, prob.nbl, prob.vmax,
+                     prob.src_coords, prob.rec_coords, device=dev, checkpoint_every=K, rc=prob.rc)
+    md.set_m(prob.fields["m"])
+    return md
+
+
+def ogrid(prob):
+    return oracle.Grid(prob.shape, prob.extent, prob.origin, so=prob.so, dt=prob.dt, nbl=prob.nbl, vmax=prob.vmax,
+                       rc=prob.rc)
+
+
+@pytest.mark.parametrize("ndim,so", [(3, 8), (2, 4), (3, 4)])
+def test_adjoint_matches_oracle_and_dot_test(dev, ndim, so):
+    prob = problem(ndim, so, 45, 90 + so)
+    rng = np.random.default_rng(7)
+    d = rng.standard_normal((prob.nt, prob.rec_coords.shape[0])).astype(np.float32).astype(np.float64)
+    say("adjoint", ndim, so)
+    md = model_for(prob, dev, 10)
+    try:
+        fq = md.forward(prob.src).cpu().numpy().astype(np.float64)
+        ftd = md.adjoint(d).cpu().numpy().astype(np.float64)
+    finally:
+        md.close()
+    g = ogrid(prob)
+    ref = oracle.iso_adjoint(g, prob.fields["m"], prob.nt, prob.src_coords, prob.rec_coords, d)
+    e = rel_l2(ftd, ref)
+    lhs, rhs = float(np.sum(fq * d)), float(np.sum(prob.src * ftd))
+    dot = abs(lhs - rhs) / abs(lhs)
+    say("adjoint rel L2", f"{e:.2e}", "dot test", f"{dot:.2e}")
+    assert e <= 1e-4
+    assert dot <= 1e-5
+
+
+@pytest.mark.parametrize("ndim,so", [(3, 8), (2, 4)])
+def test_gradient_matches_oracle(dev, ndim, so):
+    prob = problem(ndim, so, 40, 120 + so)
+    rng = np.random.default_rng(8)
+    d = rng.standard_normal((prob.nt, prob.rec_coords.shape[0])).astype(np.float32).astype(np.float64)
+    say("gradient", ndim, so)
+    md = model_for(prob, dev, 7)
+    try:
+        md.forward(prob.src)
+        grad = md.gradient(d).cpu().numpy().astype(np.float64)
+    finally:
+        md.close()
+    ref = oracle.iso_gradient(ogrid(prob), prob.fields["m"], prob.nt, prob.src_coords, prob.src,
+                              prob.rec_coords, d)
+    e = rel_l2(grad, ref)
+    say("gradient rel L2", f"{e:.2e}")
+    assert e <= 1e-3
+
+
+def test_gradient_independent_of_checkpoint_interval(dev):
+    prob = problem(3, 8, 36, 150)
+    rng = np.random.default_rng(9)
+    d = rng.standard_normal((prob.nt, prob.rec_coords.shape[0]))
+    out = []
+    for K in (prob.nt, 5, 11):
+        md = model_for(prob, dev, K)
+        try:
+            md.forward(prob.src)
+            out.append(md.gradient(d).cpu().numpy())
+        finally:
+            md.close()
+    say("checkpoint intervals", [float(np.abs(o).max()) for o in out])
+    np.testing.assert_array_equal(out[0], out[1])
+    np.testing.assert_array_equal(out[0], out[2])
+
+
+def test_autograd_finite_difference(dev):
+    """0.5 ||F(m) q - d_obs||^2: autograd gradient along a smooth direction
+    against a central difference of the GPU objective (FP32)."""
+    import torch
+    from paper_1807_03032_amd.modeling import wave_forward_function
+
+    prob = problem(3, 4, 60, 170, nrec=25)
+    md = model_for(prob, dev, 12)
+    try:
+        Fw = wave_forward_function()
+        m0 = torch.tensor(prob.fields["m"], dtype=torch.float32, device=dev)
+        q = torch.tensor(prob.src, dtype=torch.float32, device=dev)
+        with torch.no_grad():
+            d_obs = Fw.apply(m0 * 1.02, q, md).clone()
+
+        def loss(mm):
+            return 0.5 * torch.sum((Fw.apply(mm, q, md).double() - d_obs.double()) ** 2)
+
+        m = m0.clone().requires_grad_(True)
+        L = loss(m)
+        L.backward()
+        g = m.grad.detach().double()
+        zz, yy, xx = np.meshgrid(*[np.linspace(0, 1, n) for n in prob.array_shape], indexing="ij")
+        dm = torch.tensor(np.sin(3 * xx) * np.cos(2 * yy) * np.sin(2 * zz + 0.5), dtype=torch.float64,
+                          device=dev) * m0.double() * 1e-3
+        with torch.no_grad():
+            lp = float(loss((m0.double() + dm).float()))
+            lm = float(loss((m0.double() - dm).float()))
+        fd = (lp - lm) / 2.0
+        an = float(torch.sum(g * dm))
+        say("autograd fd", fd, "analytic", an)
+        assert abs(fd - an) <= 2e-2 * abs(an)
+    finally:
+        md.close()
