@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--nslots", type=int, default=2, choices=(2, 3),
                     help="wavefield storage of the isotropic workload: 2 = in-place leapfrog (default), "
                          "3 = modulo-3 buffer u[t %% 3]")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time one gradient (forward with checkpoints + recomputation + adjoint + imaging) "
+                         "on the 320^3 so=8 1500-step workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -95,6 +98,48 @@ def parity_vs_stored(name, prob, steps, tr, f):
     ref = z["rec_val"]
     out["rec"] = float(np.linalg.norm(tr[:, z["rec_idx"]] - ref) / np.linalg.norm(ref))
     return out
+
+
+def adjoint_leg(device, checkpoint_every=50):
+    """One full-waveform gradient on the 320^3 workload: observed data from the
+    true model, then forward (checkpoints every 50 steps) at the background
+    model, residual, and the checkpointed adjoint-state gradient.  Also the
+    FP32 adjoint dot-product test on this geometry."""
+    import numpy as np
+    import torch
+
+    from paper_1807_03032_amd import workloads as W
+    from paper_1807_03032_amd.modeling import IsoModeling
+
+    prob, m_true = W.config_3d_iso_adjoint_320()
+    md = IsoModeling(prob.shape, prob.extent, prob.origin, prob.so, prob.dt, prob.nt, prob.nbl, prob.vmax,
+                     prob.src_coords, prob.rec_coords, device=device, checkpoint_every=checkpoint_every, rc=prob.rc)
+    try:
+        md.set_m(m_true)
+        d_obs = md.forward(prob.src, checkpoints=False)
+        md.set_m(prob.fields["m"])
+        torch.cuda.synchronize(device)
+        t0 = time.perf_counter()
+        resid = md.forward(prob.src, checkpoints=True) - d_obs
+        torch.cuda.synchronize(device)
+        t1 = time.perf_counter()
+        g = md.gradient(resid)
+        torch.cuda.synchronize(device)
+        t2 = time.perf_counter()
+        # dot test on this geometry: <F q, d> vs <q, F^T d> with d = the residual
+        ftd = md.adjoint(resid)
+        fq = md.forward(prob.src, checkpoints=False)
+        lhs = float(torch.sum(fq.double() * resid.double()))
+        rhs = float(torch.sum(torch.as_tensor(prob.src, device=device).double() * ftd.double()))
+        gn = float(torch.linalg.norm(g.double()))
+    finally:
+        md.close()
+    n = prob.npoints * prob.nt
+    return {"workload": "3D isotropic 320^3, h=10 m, so=8, nbl=40, 1500 steps, smooth background + 5% perturbation, "
+                        "320x320 receivers, checkpoints every 50 steps",
+            "forward_s": round(t1 - t0, 4), "gradient_s": round(t2 - t1, 4),
+            "gradient_GPts_per_s": round(n / (t2 - t0) / 1e9, 3),
+            "dot_test_rel": abs(lhs - rhs) / abs(lhs), "grad_norm": gn}
 
 
 def cpu_baseline(prob, nsteps):
@@ -287,6 +332,8 @@ def main():
         p2 = parity_vs_stored("3d_tti_512", pt, pt.nt, tr2, f2)
         if p2 is not None:
             line["tti"]["parity_rel_l2_sampled"] = p2
+    if args.adjoint:
+        line["adjoint"] = adjoint_leg(dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     if os.environ.get("FDW_BENCH_OPS_OUT"):

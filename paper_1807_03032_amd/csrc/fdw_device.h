@@ -95,6 +95,39 @@ __device__ __forceinline__ float damp_at(const float *ex, const float *ey, const
     }
 
 // ---------------------------------------------------------------------------
+// Sparse-point helpers (receiver sampling can run inside a stencil launch)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t corner_offset(const SparseArgs &a, int c) {
+    return ((c & 1) ? a.cstride[0] : 0) + ((c & 2) ? a.cstride[1] : 0) + ((c & 4) ? a.cstride[2] : 0);
+}
+
+// damping factor a = eta dt / 2 at corner c of sparse point p (adjoint modes)
+__device__ __forceinline__ float corner_damp(const SparseArgs &a, int p, int c) {
+    const int *b = a.idx + 3 * p;
+    const int x = b[0] + (c & 1);
+    if (a.ndim == 3) return a.eta_x[x] + a.eta_y[b[1] + ((c >> 1) & 1)] + a.eta_z[b[2] + ((c >> 2) & 1)];
+    return a.eta_x[x] + a.eta_z[b[2] + ((c >> 1) & 1)];
+}
+
+// Receiver sampling for one lane: group of ncorner lanes per receiver, lane
+// c owns corner c, the group's products are reduced with cross-lane shuffles
+// (groups of 4 or 8 lanes are aligned inside the 64-wide wavefront).
+__device__ __forceinline__ void interp_lane(const SparseArgs &a, int lane) {
+    const int p = lane / a.ncorner;
+    const int c = lane % a.ncorner;
+    float v = 0.0f;
+    if (p < a.npoint) {
+        v = a.w[(int64_t)p * a.ncorner + c] * a.field[a.base[p] + corner_offset(a, c)];
+        if (a.damp_mode == 2) v *= 1.0f + corner_damp(a, p, c);
+    }
+    // groups of 4 or 8 lanes are aligned inside the 64-wide wavefront
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    if (a.ncorner == 8) v += __shfl_xor(v, 4);
+    if (p < a.npoint && c == 0) a.rec_row[p] = v;
+}
+
+// ---------------------------------------------------------------------------
 // 3D z-streaming engine (2.5D blocking), shared by the isotropic step and the
 // two TTI stages.
 //
@@ -156,14 +189,20 @@ struct StreamPoint {
 
 template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
 __global__ void __launch_bounds__(64 * BY) stream3d(Op op, StreamFields<NQ, NP> F, Geom g, int zc, int ntx, int nty,
-                                                   int zfast) {
+                                                   int zfast, SparseArgs sp, int nb_stencil) {
     constexpr int NT = 64 * BY;  // threads per workgroup
+    // workgroups past the stencil tiles sample the receivers of the previous
+    // step from the current level, which this launch only reads
+    if ((int)blockIdx.x >= nb_stencil) {
+        interp_lane(sp, ((int)blockIdx.x - nb_stencil) * NT + (int)threadIdx.x);
+        return;
+    }
     constexpr int TX = 64, TY = BY * NY, LW = TX + 2 * R, LH = TY + 2 * R, Q = 2 * R + 1;
     constexpr int NHY = (2 * R + BY - 1) / BY;       // y-halo rows per wavefront
     constexpr int NHX = (TY * 2 * R + NT - 1) / NT;  // x-halo elements per thread
     __shared__ float lds[2][NQ][LH][LW];
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-    int tile = xcd_tile(blockIdx.x, gridDim.x);
+    int tile = xcd_tile(blockIdx.x, nb_stencil);
     int tx, ty, tz;
     if (zfast) {  // z-chunk fastest: every chunk of a column on one XCD
         const int ntz = (g.nz + zc - 1) / zc;
@@ -349,14 +388,20 @@ struct DampTables {
 
 template <int R, int NY, int PF, int BY, int NQ, int NP, class Op>
 static hipError_t launch_stream3d(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s,
-                                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+                                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, const SparseArgs *sp = nullptr) {
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + BY * NY - 1) / (BY * NY), ntz = (g.nz + zc - 1) / zc;
     const int64_t nb = (int64_t)ntx * nty * ntz;
+    SparseArgs spv{};
+    int64_t ni = 0;  // extra workgroups for receiver sampling
+    if (sp && sp->npoint > 0) {
+        spv = *sp;
+        ni = ((int64_t)sp->npoint * sp->ncorner + 64 * BY - 1) / (64 * BY);
+    }
     // tile order: FDW_TILE_ORDER=z puts the z-chunk index fastest (tuning knob)
     const char *order = std::getenv("FDW_TILE_ORDER");
     const int zfast = (order && order[0] == 'z') ? 1 : 0;
-    hipExtLaunchKernelGGL((stream3d<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)nb), dim3(64 * BY), 0, s, e0, e1, 0, op,
-                          F, g, zc, ntx, nty, zfast);
+    hipExtLaunchKernelGGL((stream3d<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)(nb + ni)), dim3(64 * BY), 0, s, e0, e1,
+                          0, op, F, g, zc, ntx, nty, zfast, spv, (int)nb);
     return hipGetLastError();
 }
 

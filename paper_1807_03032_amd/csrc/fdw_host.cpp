@@ -124,6 +124,10 @@ struct fdw_op {
     double acc_ms = 0.0;
     int64_t acc_launches = 0;
     hipStream_t last_stream = nullptr;
+    // receiver sampling overlapped with the next steps on a second stream
+    bool overlap_interp = false;
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> ev_step, ev_interp;  // ring of nslots + 1 each
 };
 
 // ---------------------------------------------------------------------------
@@ -399,6 +403,12 @@ static void release_device(fdw_op *op) {
     op->d_src_idx = op->d_rec_idx = nullptr;
     for (hipEvent_t e : op->ev_pool) (void)hipEventDestroy(e);
     op->ev_pool.clear();
+    for (hipEvent_t e : op->ev_step) (void)hipEventDestroy(e);
+    for (hipEvent_t e : op->ev_interp) (void)hipEventDestroy(e);
+    op->ev_step.clear();
+    op->ev_interp.clear();
+    if (op->side) (void)hipStreamDestroy(op->side);
+    op->side = nullptr;
     op->d_eta = op->d_stage = op->d_src_w = op->d_rec_w = nullptr;
     op->d_src_base = op->d_rec_base = nullptr;
 }
@@ -634,6 +644,30 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
     }
 
     pick_variants(op);
+    // Receiver sampling of step t reads level t+1, which the stencil of step
+    // t + S (S = slots) overwrites: it can run on a second stream, overlapped with
+    // the next stencil launches, ordered by events (opt-in, FDW_OVERLAP_INTERP=1:
+    // the cross-stream waits cost more than the overlap saves on one MI355X).
+    {
+        const char *ov = std::getenv("FDW_OVERLAP_INTERP");
+        op->overlap_interp = op->ndim == 3 && d.rec && d.rec->npoint >= 1024 && ov && ov[0] == '1';
+        if (op->overlap_interp) {
+            const int ring = d.u->nslots + 1;
+            hipError_t e2 = hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking);
+            for (int i = 0; e2 == hipSuccess && i < ring; ++i) {
+                hipEvent_t a = nullptr, b = nullptr;
+                e2 = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+                if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+                if (a) op->ev_step.push_back(a);
+                if (b) op->ev_interp.push_back(b);
+            }
+            if (e2 != hipSuccess) {
+                release_device(op);
+                delete op;
+                return fail_hip(e2, "operator_create: side stream");
+            }
+        }
+    }
     // reference counts keep bound handles alive while the operator exists
     d.u->refs++;
     if (d.r) d.r->refs++;
@@ -754,7 +788,19 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         if (op->timing) op->acc_launches++;
         return FDW_OK;
     }
+    const int S_ring = d.u->nslots + 1;
+    // the 3D streaming kernels sample the receivers of step t - 1 inside the
+    // launch of step t (extra workgroups reading level t); the last step of the
+    // apply is sampled by its own launch after the loop
+    const bool fuse_interp = nrec > 0 && op->ndim == 3 && !op->overlap_interp &&
+                             (d.kind == FDW_ISO ? op->iso_v == IsoVariant::Stream : op->tti_v == TtiVariant::Stream);
     for (int t = time_m; t <= time_M; ++t) {
+        // the stencil of step t overwrites the slot of level t + 1 - S, which
+        // the (overlapped) receiver sampling of step t - S reads
+        if (op->overlap_interp && nrec > 0 && t - d.u->nslots >= time_m) {
+            hipError_t er = hipStreamWaitEvent(s, op->ev_interp[(t - d.u->nslots) % S_ring], 0);
+            if (er != hipSuccess) return fail_hip(er, "operator_apply: hipStreamWaitEvent");
+        }
         // level k lives in slot k mod S; with S = 2 the new level overwrites t - 1
         const int S = d.u->nslots;
         const int sc = t % S, sp = (t + S - 1) % S, sn = (t + 1) % S;
@@ -786,6 +832,13 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             a.src = fs;
             a.adjoint = d.mode == FDW_ADJOINT;
             a.save = nullptr;
+            SparseArgs prev_itp = itp;
+            a.rec = nullptr;
+            if (fuse_interp && t > time_m) {
+                prev_itp.field = const_cast<float *>(a.u_cur);  // level t, read-only in this launch
+                prev_itp.rec_row = d.rec->data + (int64_t)(t - 1) * nrec;
+                a.rec = &prev_itp;
+            }
             const int L = t + 1;
             if (op->save_buf && L >= op->save_first && (L - op->save_first) % op->save_every == 0 &&
                 (L - op->save_first) / op->save_every < op->save_nlevels) {
@@ -816,6 +869,13 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             a.dt2 = op->dt2;
             a.c = op->coefs;
             a.src = fs;
+            SparseArgs prev_itp = itp;
+            a.rec = nullptr;
+            if (fuse_interp && t > time_m) {
+                prev_itp.field = const_cast<float *>(a.p_cur);  // level t, read-only in this launch
+                prev_itp.rec_row = d.rec->data + (int64_t)(t - 1) * nrec;
+                a.rec = &prev_itp;
+            }
             e = launch_tti(op->ndim, op->R, op->tti_v, a, s, ev);
             next_field = a.p_next;
         }
@@ -834,10 +894,27 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             e = hipMemcpyAsync(save_dst, next_field, sizeof(float) * (size_t)E, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return fail_hip(e, "operator_apply: save copy");
         }
-        if (nrec > 0) {
+        if (nrec > 0 && (!fuse_interp || t == time_M)) {
             itp.field = next_field;
             itp.rec_row = d.rec->data + (int64_t)t * nrec;
-            if ((e = launch_interp(itp, s)) != hipSuccess) return fail_hip(e, "operator_apply: interp launch");
+            if (op->overlap_interp) {
+                hipEvent_t es = op->ev_step[t % S_ring], ei = op->ev_interp[t % S_ring];
+                hipError_t er = hipEventRecord(es, s);
+                if (er == hipSuccess) er = hipStreamWaitEvent(op->side, es, 0);
+                if (er != hipSuccess) return fail_hip(er, "operator_apply: side-stream ordering");
+                if ((e = launch_interp(itp, op->side)) != hipSuccess) return fail_hip(e, "operator_apply: interp launch");
+                if ((er = hipEventRecord(ei, op->side)) != hipSuccess) return fail_hip(er, "operator_apply: hipEventRecord");
+            } else if ((e = launch_interp(itp, s)) != hipSuccess) {
+                return fail_hip(e, "operator_apply: interp launch");
+            }
+        }
+    }
+    // the caller's stream covers every receiver sample of this apply
+    if (op->overlap_interp && nrec > 0 && time_M >= time_m) {
+        const int last = std::max(time_m, time_M - d.u->nslots + 1);
+        for (int t = last; t <= time_M; ++t) {
+            hipError_t er = hipStreamWaitEvent(s, op->ev_interp[t % S_ring], 0);
+            if (er != hipSuccess) return fail_hip(er, "operator_apply: hipStreamWaitEvent");
         }
     }
     return FDW_OK;

@@ -53,6 +53,7 @@ struct IsoArgs {
     FusedSrc src;
     int adjoint;   // 1: injected terms are divided by the damping factor (1 + a)
     float *save;   // optional: the new level is also stored here (same layout)
+    const struct SparseArgs *rec;  // optional: receiver sampling of the previous step
 };
 
 struct TtiArgs {
@@ -65,6 +66,7 @@ struct TtiArgs {
     float dt2;
     Coefs c;
     FusedSrc src;
+    const struct SparseArgs *rec;  // optional: receiver sampling of the previous step
 };
 
 struct SparseArgs {

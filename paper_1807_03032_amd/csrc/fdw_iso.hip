@@ -241,7 +241,7 @@ static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t 
     F.p[1] = a.m;
     F.pout[0] = 0.0f;
     F.pout[1] = 1.0f;
-    return launch_stream3d<R, NY, PF, BY>(op, F, a.g, zc, s, ev.start, ev.stop);
+    return launch_stream3d<R, NY, PF, BY>(op, F, a.g, zc, s, ev.start, ev.stop, a.rec);
 }
 
 template <int R, int NY, int PF>

@@ -12,32 +12,8 @@ namespace fdw {
 // shuffles; injection scatters with atomics (sources may share points).
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int64_t corner_offset(const SparseArgs &a, int c) {
-    return ((c & 1) ? a.cstride[0] : 0) + ((c & 2) ? a.cstride[1] : 0) + ((c & 4) ? a.cstride[2] : 0);
-}
-
-// damping factor a = eta dt / 2 at corner c of sparse point p (adjoint modes)
-__device__ __forceinline__ float corner_damp(const SparseArgs &a, int p, int c) {
-    const int *b = a.idx + 3 * p;
-    const int x = b[0] + (c & 1);
-    if (a.ndim == 3) return a.eta_x[x] + a.eta_y[b[1] + ((c >> 1) & 1)] + a.eta_z[b[2] + ((c >> 2) & 1)];
-    return a.eta_x[x] + a.eta_z[b[2] + ((c >> 1) & 1)];
-}
-
 __global__ void __launch_bounds__(256) interp_kernel(SparseArgs a) {
-    const int lane = blockIdx.x * blockDim.x + threadIdx.x;
-    const int p = lane / a.ncorner;
-    const int c = lane % a.ncorner;
-    float v = 0.0f;
-    if (p < a.npoint) {
-        v = a.w[(int64_t)p * a.ncorner + c] * a.field[a.base[p] + corner_offset(a, c)];
-        if (a.damp_mode == 2) v *= 1.0f + corner_damp(a, p, c);
-    }
-    // groups of 4 or 8 lanes are aligned inside the 64-wide wavefront
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    if (a.ncorner == 8) v += __shfl_xor(v, 4);
-    if (p < a.npoint && c == 0) a.rec_row[p] = v;
+    interp_lane(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) inject_kernel(SparseArgs a) {

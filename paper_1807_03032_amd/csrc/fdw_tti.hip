@@ -215,24 +215,25 @@ static TtiShape tti_stream_shape(const Geom &g) {
 
 template <int R, int NY, int BY, class Op, int NQ, int NP>
 static hipError_t launch_tti_stage(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s,
-                                   hipEvent_t e0, hipEvent_t e1) {
-    return launch_stream3d<R, NY, 1, BY>(op, F, g, zc, s, e0, e1);
+                                   hipEvent_t e0, hipEvent_t e1, const SparseArgs *sp) {
+    return launch_stream3d<R, NY, 1, BY>(op, F, g, zc, s, e0, e1, sp);
 }
 
 // Tuning variants are instantiated for R = 6 (space order 12) only; other
 // orders use (NY, BY) = (2, 8) for stage 1 and (1, 8) for stage 2.
 template <int R, class Op, int NQ, int NP>
 static hipError_t launch_tti_stage_shape(int ny, int by, const Op &op, const StreamFields<NQ, NP> &F, const Geom &g,
-                                         int zc, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                                         int zc, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                                         const SparseArgs *sp = nullptr) {
     if constexpr (R == 6) {
         if (ny == 2)
-            return by == 8 ? launch_tti_stage<R, 2, 8>(op, F, g, zc, s, e0, e1)
-                           : launch_tti_stage<R, 2, 4>(op, F, g, zc, s, e0, e1);
-        return by == 8 ? launch_tti_stage<R, 1, 8>(op, F, g, zc, s, e0, e1)
-                       : launch_tti_stage<R, 1, 4>(op, F, g, zc, s, e0, e1);
+            return by == 8 ? launch_tti_stage<R, 2, 8>(op, F, g, zc, s, e0, e1, sp)
+                           : launch_tti_stage<R, 2, 4>(op, F, g, zc, s, e0, e1, sp);
+        return by == 8 ? launch_tti_stage<R, 1, 8>(op, F, g, zc, s, e0, e1, sp)
+                       : launch_tti_stage<R, 1, 4>(op, F, g, zc, s, e0, e1, sp);
     } else {
-        if (NQ == 2) return launch_tti_stage<R, 2, 8>(op, F, g, zc, s, e0, e1);
-        return launch_tti_stage<R, 1, 8>(op, F, g, zc, s, e0, e1);
+        if (NQ == 2) return launch_tti_stage<R, 2, 8>(op, F, g, zc, s, e0, e1, sp);
+        return launch_tti_stage<R, 1, 8>(op, F, g, zc, s, e0, e1, sp);
     }
 }
 
@@ -249,7 +250,7 @@ static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s, const Lau
     F1.p[0] = a.theta;
     F1.p[1] = a.phi;
     F1.pout[0] = F1.pout[1] = 0.0f;
-    hipError_t e = launch_tti_stage_shape<R>(sh.ny1, sh.by1, o1, F1, a.g, sh.zc, s, ev.start, nullptr);
+    hipError_t e = launch_tti_stage_shape<R>(sh.ny1, sh.by1, o1, F1, a.g, sh.zc, s, ev.start, nullptr, a.rec);
     if (e != hipSuccess) return e;
     TtiS2Op o2;
     o2.c = a.c;

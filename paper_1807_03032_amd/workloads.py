@@ -235,3 +235,29 @@ def small_problem(kind: str, shape, so: int, nt: int, seed: int = 0, nsrc: int =
     return Problem(f"small_{kind}_{'x'.join(map(str, shape))}_so{so}", kind, shape, extent, (0.0,) * ndim,
                    so, nbl, nt, dt, vmax, eps_max, fields, src_coords, f32(src).reshape(nt, ns),
                    np.asarray(rec_coords, dtype=np.float64).reshape(-1, ndim))
+
+
+def config_3d_iso_adjoint_320(nt: Optional[int] = None, n: int = 320):
+    """Adjoint / gradient workload: 3D isotropic, n^3 (320^3), h = 10 m, so = 8,
+    nbl = 40, 1500 steps; smooth random background velocity in [1500, 3500] m/s
+    (seed 21, sigma = 10 points) and a true model with a 5 % smooth seeded
+    perturbation (seed 22); 10 Hz Ricker at the centre near the surface;
+    320 x 320 jittered receiver plane (seeds 23-25).
+
+    Returns (background problem, true squared slowness)."""
+    shape, h, nbl = (n, n, n), 10.0, 40
+    nt = 1500 if nt is None else nt
+    extent = tuple(h * (k - 1) for k in shape)
+    v_bg = smooth_field(shape, 21, 1500.0, 3500.0)
+    pert = smooth_field(shape, 22, -1.0, 1.0)
+    v_true = v_bg * (1.0 + 0.05 * pert)
+    vmax = 3500.0 * 1.05
+    fields, _ = _physical_models("iso", shape, v_bg, 0)
+    m_true = f32(1.0 / (v_true * v_true))
+    dt = cfl_dt(h, vmax, 3)
+    src_coords = np.array([[extent[0] / 2, extent[1] / 2, (nbl + 2.5) * h]])
+    src = ricker(10.0, 0.1, dt, nt)[:, None]
+    rec_coords = _receiver_plane(n, n, h, extent[0], extent[1], (nbl + 2) * h, (23, 24, 25))
+    prob = Problem(f"3d_iso_adjoint_{n}cube_so8", "iso", shape, extent, (0.0,) * 3, 8, nbl, nt, dt, vmax, 0.0,
+                   fields, src_coords, f32(src), rec_coords)
+    return prob, m_true
