@@ -49,7 +49,7 @@ def parse():
     return ap.parse_args()
 
 
-def time_shot(prob, steps, warmup, device, nslots=3):
+def time_shot(prob, steps, warmup, device, nslots=3, timing_every=10):
     """Warm up, reset to the zero initial state, then time `steps` time steps."""
     import torch
 
@@ -63,7 +63,9 @@ def time_shot(prob, steps, warmup, device, nslots=3):
     for t in shot.wave.values():
         t.zero_()
     shot.rec_data.zero_()
-    fdw.fdw_operator_set_timing(shot.op, True)
+    # HIP events on one stencil launch in every `timing_every` (each bracketed
+    # launch costs the stream a few microseconds)
+    fdw.fdw_operator_set_timing(shot.op, timing_every)
     torch.cuda.synchronize(device)
     t0 = time.perf_counter()
     lo = 0

@@ -217,11 +217,14 @@ int fdw_gradient_accumulate(fdw_op *op, const float *nu, const float *u_next, co
 int fdw_sync(fdw_op *op);
 int fdw_operator_destroy(fdw_op *op);
 
-/* Per-kernel timing (measurement support).  When enabled, apply brackets every
- * launch of the operator's dominant stencil kernel with a pair of HIP events on
- * the apply stream; fdw_operator_kernel_time synchronises and returns the
- * summed milliseconds and the number of launches since the last reset.
- * Errors: FDW_ERR_ARG, FDW_ERR_DEVICE. */
+/* Per-kernel timing (measurement support).  enable = k > 0 brackets one launch
+ * in every k of the operator's dominant stencil kernel (counting from the first
+ * launch after this call; k = 1: every launch) with a pair of HIP events on the
+ * apply stream; 0 disables.  Events cost the stream a few microseconds per
+ * bracketed launch, so sampling keeps that cost out of a timed loop.
+ * fdw_operator_kernel_time synchronises and returns the summed milliseconds and
+ * the number of bracketed launches since the last reset.
+ * Errors: FDW_ERR_ARG (NULL op, k < 0), FDW_ERR_DEVICE. */
 int fdw_operator_set_timing(fdw_op *op, int enable);
 int fdw_operator_kernel_time(fdw_op *op, double *total_ms, int64_t *launches, int reset);
 

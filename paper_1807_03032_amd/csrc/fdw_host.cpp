@@ -119,6 +119,8 @@ struct fdw_op {
     bool src_fused = false;
     // timing
     bool timing = false;
+    int timing_every = 1;    // one stencil launch in every timing_every carries events
+    int64_t timing_seq = 0;  // stencil launches since timing was enabled
     std::vector<hipEvent_t> ev_pool;  // pairs
     size_t ev_used = 0;
     double acc_ms = 0.0;
@@ -779,13 +781,14 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         pa.rec_w = op->d_rec_w;
         pa.rec_data = nrec > 0 ? d.rec->data : nullptr;
         LaunchEvents ev;
-        if (op->timing) {
+        const bool timed = op->timing && op->timing_seq++ % op->timing_every == 0;
+        if (timed) {
             int st = timing_event_pair(op, &ev.start, &ev.stop);
             if (st) return st;
         }
         hipError_t e = launch_iso2d_persistent(op->R, pa, s, ev);
         if (e != hipSuccess) return fail_hip(e, "operator_apply: persistent 2D launch");
-        if (op->timing) op->acc_launches++;
+        if (timed) op->acc_launches++;
         return FDW_OK;
     }
     const int S_ring = d.u->nslots + 1;
@@ -810,7 +813,8 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             fs.q = d.src->data + (int64_t)t * nsrc;
         }
         LaunchEvents ev;
-        if (op->timing) {
+        const bool timed = op->timing && op->timing_seq++ % op->timing_every == 0;
+        if (timed) {
             int st = timing_event_pair(op, &ev.start, &ev.stop);
             if (st) return st;
         }
@@ -880,7 +884,7 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             next_field = a.p_next;
         }
         if (e != hipSuccess) return fail_hip(e, "operator_apply: stencil launch");
-        if (op->timing) op->acc_launches++;
+        if (timed) op->acc_launches++;
         if (nsrc > 0 && !op->src_fused) {
             inj.q_row = d.src->data + (int64_t)t * nsrc;
             inj.field = next_field;
@@ -961,7 +965,10 @@ int fdw_sync(fdw_op *op) {
 
 int fdw_operator_set_timing(fdw_op *op, int enable) {
     if (!op) return fail(FDW_ERR_ARG, "set_timing: NULL op");
+    if (enable < 0) return fail(FDW_ERR_ARG, "set_timing: negative sampling interval %d", enable);
     op->timing = enable != 0;
+    op->timing_every = enable > 0 ? enable : 1;
+    op->timing_seq = 0;
     op->ev_used = 0;
     op->acc_ms = 0.0;
     op->acc_launches = 0;

@@ -209,7 +209,8 @@ def fdw_gradient_accumulate(op, nu: int, u_next: int, u_cur: int, u_prev: int, g
     _chk(load().fdw_gradient_accumulate(op, nu, u_next, u_cur, u_prev, grad, stream))
 
 
-def fdw_operator_set_timing(op, enable: bool):
+def fdw_operator_set_timing(op, enable):
+    """enable: False/0 off, True/1 every launch, k > 1 one launch in every k."""
     _chk(load().fdw_operator_set_timing(op, int(enable)))
 
 
