@@ -10,6 +10,7 @@
  *   domain / halo / padding regions             -> fdw_field_layout       (Section 3.6)
  *   SparseTimeFunction(coordinates), inject,
  *   interpolate                                 -> fdw_sparse_bind        (Section 3.3)
+ *   PrecomputedSparseFunction                   -> fdw_sparse_bind_precomputed (Section 3.3)
  *   Operator(eqs) ... op.apply(time=...)        -> fdw_operator_create,
  *                                                  fdw_operator_apply     (Section 4 intro, 4.8)
  *
@@ -53,6 +54,7 @@ extern "C" {
 #define FDW_TTI 1 /* TTI pseudo-acoustic: coupled p, r with rotated operators      */
 
 #define FDW_MAX_SO 16
+#define FDW_MAX_SUPPORT 4 /* support points per axis of a precomputed sparse function */
 #define FDW_X_OFFSET 32 /* floats before logical x = 0 in each row (128-byte alignment) */
 
 typedef struct fdw_grid fdw_grid;
@@ -169,6 +171,22 @@ int fdw_timefunction_destroy(fdw_tfunc *f);
  * Errors: FDW_ERR_ARG, FDW_ERR_DOMAIN, FDW_ERR_NOMEM, FDW_ERR_DEVICE. */
 int fdw_sparse_bind(fdw_grid *grid, const char *name, int npoint, int nt, const double *coords_host,
                     float *ddata, fdw_sparse **out);
+
+/* PrecomputedSparseFunction (Section 3.3: grid points and coefficients
+ * computed by the caller for a custom interpolation scheme).  Point p is
+ * supported on the r^ndim grid points gridpoints[p][a] + j_a, j_a = 0..r-1 on
+ * every axis a (axes in grid order, indices of the computational domain), with
+ * weight prod_a coeffs[p][a][j_a] (formed in double on the host).  Support
+ * point c enumerates (j_0, j_1, ...) with j_0 fastest.  Injection and
+ * interpolation use these supports and weights exactly as fdw_sparse_bind's
+ * linear ones; r = 2 with coefficients (1 - f, f) and base floor reproduces
+ * fdw_sparse_bind.  gridpoints [npoint][ndim] and coeffs [npoint][ndim][r] are
+ * host arrays (copied); ddata as for fdw_sparse_bind.
+ * Errors: FDW_ERR_ARG (r outside 1..FDW_MAX_SUPPORT, NULL), FDW_ERR_DOMAIN (a
+ * support point outside the domain), FDW_ERR_NOMEM. */
+int fdw_sparse_bind_precomputed(fdw_grid *grid, const char *name, int npoint, int nt, int r,
+                                const int64_t *gridpoints, const double *coeffs, float *ddata,
+                                fdw_sparse **out);
 int fdw_sparse_destroy(fdw_sparse *s);
 
 /* Operator construction (Section 4: built once, applied many times).
@@ -199,7 +217,8 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream);
  * the isotropic operator runs, every level L >= first_level with
  * (L - first_level) % every == 0 and k = (L - first_level) / every < nlevels
  * is also stored in buf + k * elems_per_slot (same layout; halos untouched).
- * Level L is the one step L - 1 computes (after injection).  buf = NULL
+ * Level L is the one step L - 1 computes (after injection); the initial level
+ * 0 (slot 0) is stored when an apply starts at time_m = 0.  buf = NULL
  * disables saving.  The store is fused into the stencil kernel when the sources
  * are fused.  Errors: FDW_ERR_ARG (TTI operator, every < 1, nlevels < 0). */
 int fdw_operator_set_save(fdw_op *op, float *buf, int64_t nlevels, int every, int first_level);

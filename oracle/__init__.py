@@ -193,6 +193,70 @@ def inject(grid: Grid, coords, q, u, scale=1.0, m=None) -> np.ndarray:
     return u
 
 
+def _pre(grid, gridpoints, coeffs):
+    gp = np.ascontiguousarray(np.asarray(gridpoints, dtype=np.int64).reshape(-1, grid.ndim))
+    cf = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+    if cf.ndim != 3 or cf.shape[:2] != gp.shape:
+        raise ValueError(f"coeffs shape {cf.shape} does not match gridpoints {gp.shape}")
+    return gp, cf, int(cf.shape[2])
+
+
+def _lptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_long)) if a is not None else None
+
+
+def interp_pre(grid: Grid, gridpoints, coeffs, u) -> np.ndarray:
+    """Precomputed sparse points: out[p] = sum over the r^d support points."""
+    gp, cf, r = _pre(grid, gridpoints, coeffs)
+    u = _field(grid, u)
+    out = np.zeros(gp.shape[0])
+    g = grid.c()
+    _check(_load().or_interp_pre(ctypes.byref(g), ctypes.c_int(gp.shape[0]), ctypes.c_int(r), _lptr(gp), _ptr(cf),
+                                 _ptr(u), _ptr(out)), "interp_pre")
+    return out
+
+
+def inject_pre(grid: Grid, gridpoints, coeffs, q, u, scale=1.0, m=None) -> np.ndarray:
+    gp, cf, r = _pre(grid, gridpoints, coeffs)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    u = _field(grid, u).copy()
+    mm = _field(grid, m) if m is not None else None
+    g = grid.c()
+    _check(_load().or_inject_pre(ctypes.byref(g), ctypes.c_int(gp.shape[0]), ctypes.c_int(r), _lptr(gp), _ptr(cf),
+                                 _ptr(q), ctypes.c_double(scale), _ptr(mm), _ptr(u)), "inject_pre")
+    return u
+
+
+def iso_run_pre(grid: Grid, m, nt: int, src_pre, src, rec_pre, u_prev=None, u_cur=None, time_m: int = 0,
+                time_M: int | None = None):
+    """iso_run with precomputed sparse points: src_pre / rec_pre are
+    (gridpoints, coeffs) pairs or None."""
+    if time_M is None:
+        time_M = nt - 1
+    m = _field(grid, m)
+    up = _field(grid, u_prev).copy() if u_prev is not None else np.zeros(grid.array_shape)
+    uc = _field(grid, u_cur).copy() if u_cur is not None else np.zeros(grid.array_shape)
+    ns, sr, sgp, scf, sd = 0, 1, None, None, None
+    if src_pre is not None:
+        sgp, scf, sr = _pre(grid, *src_pre)
+        ns = sgp.shape[0]
+        sd = np.ascontiguousarray(src, dtype=np.float64)
+        if sd.shape != (nt, ns):
+            raise ValueError(f"src data shape {sd.shape} != {(nt, ns)}")
+    nr, rr, rgp, rcf = 0, 1, None, None
+    if rec_pre is not None:
+        rgp, rcf, rr = _pre(grid, *rec_pre)
+        nr = rgp.shape[0]
+    rec = np.zeros((nt, nr))
+    g = grid.c()
+    st = _load().or_iso_run_pre(ctypes.byref(g), _ptr(m), ctypes.c_int(time_m), ctypes.c_int(time_M), _ptr(up),
+                                _ptr(uc), ctypes.c_int(ns), ctypes.c_int(sr), _lptr(sgp), _ptr(scf), _ptr(sd),
+                                ctypes.c_int(nr), ctypes.c_int(rr), _lptr(rgp), _ptr(rcf),
+                                _ptr(rec) if nr else None)
+    _check(st, "iso_run_pre")
+    return up, uc, rec
+
+
 def rotated_h(grid: Grid, theta, phi, u) -> np.ndarray:
     u = _field(grid, u)
     th = _field(grid, theta)

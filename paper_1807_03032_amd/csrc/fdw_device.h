@@ -97,16 +97,34 @@ __device__ __forceinline__ float damp_at(const float *ex, const float *ey, const
 // ---------------------------------------------------------------------------
 // Sparse-point helpers (receiver sampling can run inside a stencil launch)
 // ---------------------------------------------------------------------------
+// support point c of a sparse point: digit k of c in base r is the offset
+// along axis k (x first)
+__device__ __forceinline__ void corner_digits(const SparseArgs &a, int c, int &j0, int &j1, int &j2) {
+    if (a.r == 2) {
+        j0 = c & 1;
+        j1 = (c >> 1) & 1;
+        j2 = (c >> 2) & 1;
+    } else {
+        j0 = c % a.r;
+        j1 = (c / a.r) % a.r;
+        j2 = c / (a.r * a.r);
+    }
+}
+
 __device__ __forceinline__ int64_t corner_offset(const SparseArgs &a, int c) {
-    return ((c & 1) ? a.cstride[0] : 0) + ((c & 2) ? a.cstride[1] : 0) + ((c & 4) ? a.cstride[2] : 0);
+    if (a.r == 2) return ((c & 1) ? a.cstride[0] : 0) + ((c & 2) ? a.cstride[1] : 0) + ((c & 4) ? a.cstride[2] : 0);
+    int j0, j1, j2;
+    corner_digits(a, c, j0, j1, j2);
+    return j0 * a.cstride[0] + j1 * a.cstride[1] + j2 * a.cstride[2];
 }
 
 // damping factor a = eta dt / 2 at corner c of sparse point p (adjoint modes)
 __device__ __forceinline__ float corner_damp(const SparseArgs &a, int p, int c) {
     const int *b = a.idx + 3 * p;
-    const int x = b[0] + (c & 1);
-    if (a.ndim == 3) return a.eta_x[x] + a.eta_y[b[1] + ((c >> 1) & 1)] + a.eta_z[b[2] + ((c >> 2) & 1)];
-    return a.eta_x[x] + a.eta_z[b[2] + ((c >> 1) & 1)];
+    int j0, j1, j2;
+    corner_digits(a, c, j0, j1, j2);
+    if (a.ndim == 3) return a.eta_x[b[0] + j0] + a.eta_y[b[1] + j1] + a.eta_z[b[2] + j2];
+    return a.eta_x[b[0] + j0] + a.eta_z[b[2] + j1];
 }
 
 // Receiver sampling for one lane: group of ncorner lanes per receiver, lane

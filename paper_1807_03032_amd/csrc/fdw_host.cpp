@@ -89,8 +89,10 @@ struct fdw_sparse {
     std::string name;
     int npoint, nt;
     float *data;                      // caller's [nt][npoint]
-    std::vector<int64_t> base;        // [npoint][ndim] grid indices
-    std::vector<double> w;            // [npoint][2^ndim] weights
+    int r = 2;                        // support points per axis
+    int ncorner = 0;                  // r^ndim
+    std::vector<int64_t> base;        // [npoint][ndim] grid indices of the first support point
+    std::vector<double> w;            // [npoint][ncorner] weights
     int refs = 0;
 };
 
@@ -372,6 +374,57 @@ int fdw_sparse_bind(fdw_grid *grid, const char *name, int npoint, int nt, const 
     s->npoint = npoint;
     s->nt = nt;
     s->data = ddata;
+    s->r = 2;
+    s->ncorner = nc;
+    s->base.swap(base);
+    s->w.swap(w);
+    grid->refs++;
+    *out = s;
+    return FDW_OK;
+    FDW_GUARD_END
+}
+
+int fdw_sparse_bind_precomputed(fdw_grid *grid, const char *name, int npoint, int nt, int r,
+                                const int64_t *gridpoints, const double *coeffs, float *ddata, fdw_sparse **out) {
+    FDW_GUARD_BEGIN
+    if (!grid || !out) return fail(FDW_ERR_ARG, "sparse_bind_precomputed: NULL grid/out");
+    if (npoint < 0 || nt < 0) return fail(FDW_ERR_ARG, "sparse_bind_precomputed: negative npoint/nt");
+    if (r < 1 || r > FDW_MAX_SUPPORT)
+        return fail(FDW_ERR_ARG, "sparse_bind_precomputed: r = %d outside [1, %d]", r, FDW_MAX_SUPPORT);
+    if (npoint > 0 && (!gridpoints || !coeffs || !ddata))
+        return fail(FDW_ERR_ARG, "sparse_bind_precomputed: NULL gridpoints/coeffs/data");
+    if (npoint > 0 && nt < 1) return fail(FDW_ERR_ARG, "sparse_bind_precomputed: nt must be >= 1");
+    const int nd = grid->ndim;
+    int nc = 1;
+    for (int a = 0; a < nd; ++a) nc *= r;
+    std::vector<int64_t> base((size_t)npoint * nd);
+    std::vector<double> w((size_t)npoint * nc);
+    for (int p = 0; p < npoint; ++p) {
+        for (int a = 0; a < nd; ++a) {
+            const int64_t b = gridpoints[(size_t)p * nd + a];
+            if (b < 0 || b + r - 1 > grid->shape[a] - 1)
+                return fail(FDW_ERR_DOMAIN, "sparse_bind_precomputed(%s): point %d axis %d support [%lld, %lld] outside [0, %lld]",
+                            name ? name : "", p, a, (long long)b, (long long)(b + r - 1), (long long)(grid->shape[a] - 1));
+            base[(size_t)p * nd + a] = b;
+        }
+        for (int c = 0; c < nc; ++c) {
+            double ww = 1.0;
+            int rest = c;
+            for (int a = 0; a < nd; ++a) {
+                ww *= coeffs[((size_t)p * nd + a) * r + rest % r];
+                rest /= r;
+            }
+            w[(size_t)p * nc + c] = ww;
+        }
+    }
+    fdw_sparse *s = new fdw_sparse();
+    s->grid = grid;
+    s->name = name ? name : "";
+    s->npoint = npoint;
+    s->nt = nt;
+    s->data = ddata;
+    s->r = r;
+    s->ncorner = nc;
     s->base.swap(base);
     s->w.swap(w);
     grid->refs++;
@@ -422,7 +475,7 @@ static int64_t element_offset(const fdw_op *op, const int64_t *idx) {
 }
 
 static int upload_sparse(fdw_op *op, const fdw_sparse *s, double scale, int64_t **d_base, float **d_w, int **d_idx) {
-    const int nc = 1 << op->ndim;
+    const int nc = s->ncorner;
     std::vector<int64_t> off(s->npoint);
     std::vector<float> w((size_t)s->npoint * nc);
     std::vector<int> idx((size_t)std::max(1, s->npoint) * 3, 0);
@@ -471,7 +524,9 @@ static void pick_variants(fdw_op *op) {
     const bool naive = k && std::strcmp(k, "naive") == 0;
     op->iso_v = naive ? IsoVariant::Naive : IsoVariant::Stream;
     op->tti_v = naive ? TtiVariant::Naive : TtiVariant::Stream;
-    op->use_persist2d = !naive && op->d.kind == FDW_ISO && op->ndim == 2 && op->d.mode == FDW_FORWARD &&
+    // the persistent kernel handles linear (2 x 2) sparse supports only
+    const bool linear = (!op->d.src || op->d.src->r == 2) && (!op->d.rec || op->d.rec->r == 2);
+    op->use_persist2d = !naive && linear && op->d.kind == FDW_ISO && op->ndim == 2 && op->d.mode == FDW_FORWARD &&
                         (int64_t)op->geom.nx * op->geom.nz * (int64_t)sizeof(float) <= kPersist2DMaxLds;
 }
 
@@ -595,7 +650,7 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
     // sparse preprocessing: element offsets and float weights
     if (d.src) {
         st = upload_sparse(op, d.src, d.dt * d.dt, &op->d_src_base, &op->d_src_w, &op->d_src_idx);
-        if (!st && d.src->npoint <= kMaxFusedSrc) {
+        if (!st && d.src->npoint <= kMaxFusedSrc && d.src->r == 2) {
             op->src_fused = true;
             FusedSrc &F = op->fsrc_template;
             std::memset(&F, 0, sizeof(F));
@@ -742,7 +797,8 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
     inj.damp_mode = d.mode == FDW_ADJOINT ? 1 : 0;
     inj.idx = op->d_src_idx;
     inj.npoint = nsrc;
-    inj.ncorner = 1 << op->ndim;
+    inj.r = d.src ? d.src->r : 2;
+    inj.ncorner = d.src ? d.src->ncorner : 1 << op->ndim;
     inj.base = op->d_src_base;
     inj.w = op->d_src_w;
     inj.cstride[0] = 1;
@@ -751,6 +807,8 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
     inj.m = d.m->d;
     SparseArgs itp = inj;
     itp.npoint = nrec;
+    itp.r = d.rec ? d.rec->r : 2;
+    itp.ncorner = d.rec ? d.rec->ncorner : 1 << op->ndim;
     itp.base = op->d_rec_base;
     itp.w = op->d_rec_w;
     itp.m = nullptr;
@@ -795,8 +853,15 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
     // the 3D streaming kernels sample the receivers of step t - 1 inside the
     // launch of step t (extra workgroups reading level t); the last step of the
     // apply is sampled by its own launch after the loop
-    const bool fuse_interp = nrec > 0 && op->ndim == 3 && !op->overlap_interp &&
+    const bool fuse_interp = nrec > 0 && op->ndim == 3 && !op->overlap_interp && interp_lanes_ok(itp) &&
                              (d.kind == FDW_ISO ? op->iso_v == IsoVariant::Stream : op->tti_v == TtiVariant::Stream);
+    // the initial level 0 is no step's output: an apply from time 0 stores it
+    if (op->save_buf && time_m == 0 && time_M >= time_m && op->save_first <= 0 && op->save_first % op->save_every == 0 &&
+        -op->save_first / op->save_every < op->save_nlevels) {
+        float *dst = op->save_buf + (int64_t)(-op->save_first / op->save_every) * E;
+        hipError_t e = hipMemcpyAsync(dst, d.u->d, sizeof(float) * (size_t)E, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return fail_hip(e, "operator_apply: save copy of level 0");
+    }
     for (int t = time_m; t <= time_M; ++t) {
         // the stencil of step t overwrites the slot of level t + 1 - S, which
         // the (overlapped) receiver sampling of step t - S reads

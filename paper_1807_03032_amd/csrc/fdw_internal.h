@@ -77,7 +77,8 @@ struct SparseArgs {
     const float *eta_x, *eta_y, *eta_z;
     int ndim;
     int npoint;
-    int ncorner;                 // 4 (2D) or 8 (3D)
+    int r;                       // support points per axis (2: linear weights)
+    int ncorner;                 // r^ndim (4 or 8 for linear weights)
     const int64_t *base;         // [npoint] element offset of corner 0
     const float *w;              // [npoint][ncorner] weights (times scale for injection)
     int64_t cstride[3];          // offsets of +axis0, +axis1, +axis2 corners
@@ -86,6 +87,9 @@ struct SparseArgs {
     const float *q_row;          // injection: samples of this step
     float *rec_row;              // interpolation: output row of this step
 };
+
+// the lane-parallel receiver sampling reduces aligned groups of 4 or 8 lanes
+inline bool interp_lanes_ok(const SparseArgs &a) { return a.r == 2 && (a.ncorner == 4 || a.ncorner == 8); }
 
 // Whole-run 2D isotropic kernel: one workgroup runs steps time_m..time_M of
 // a small 2D grid with the current level resident in LDS.

@@ -16,6 +16,20 @@ __global__ void __launch_bounds__(256) interp_kernel(SparseArgs a) {
     interp_lane(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// Receiver sampling for supports other than 4 or 8 points: one thread per
+// receiver, corners summed in order.
+__global__ void __launch_bounds__(256) interp_point_kernel(SparseArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.npoint) return;
+    float v = 0.0f;
+    for (int c = 0; c < a.ncorner; ++c) {
+        float t = a.w[(int64_t)p * a.ncorner + c] * a.field[a.base[p] + corner_offset(a, c)];
+        if (a.damp_mode == 2) t *= 1.0f + corner_damp(a, p, c);
+        v += t;
+    }
+    a.rec_row[p] = v;
+}
+
 __global__ void __launch_bounds__(256) inject_kernel(SparseArgs a) {
     const int lane = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = lane / a.ncorner;
@@ -78,6 +92,10 @@ hipError_t launch_inject(const SparseArgs &a, hipStream_t s) {
 
 hipError_t launch_interp(const SparseArgs &a, hipStream_t s) {
     if (a.npoint <= 0) return hipSuccess;
+    if (!interp_lanes_ok(a)) {
+        hipLaunchKernelGGL(interp_point_kernel, dim3((unsigned)((a.npoint + 255) / 256)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     const int64_t lanes = (int64_t)a.npoint * a.ncorner;
     hipLaunchKernelGGL(interp_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();

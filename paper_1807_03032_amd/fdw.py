@@ -41,6 +41,7 @@ EXPORTS = (
     "fdw_operator_create", "fdw_operator_apply", "fdw_sync", "fdw_operator_destroy",
     "fdw_operator_set_timing", "fdw_operator_kernel_time", "fdw_operator_describe", "fdw_stable_dt",
     "fdw_last_error", "fdw_version", "fdw_operator_set_save", "fdw_gradient_accumulate",
+    "fdw_sparse_bind_precomputed",
 )
 
 
@@ -88,6 +89,8 @@ def load(path: str = LIB_PATH):
         "fdw_timefunction_bind": (i32, [vp, ctypes.c_char_p, vp, i64, i32, i32, i32, pvp]),
         "fdw_timefunction_destroy": (i32, [vp]),
         "fdw_sparse_bind": (i32, [vp, ctypes.c_char_p, i32, i32, ctypes.POINTER(dbl), vp, pvp]),
+        "fdw_sparse_bind_precomputed": (i32, [vp, ctypes.c_char_p, i32, i32, i32, ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(dbl), vp, pvp]),
         "fdw_sparse_destroy": (i32, [vp]),
         "fdw_operator_create": (i32, [ctypes.POINTER(fdw_op_desc), pvp]),
         "fdw_operator_apply": (i32, [vp, i32, i32, vp]),
@@ -175,6 +178,24 @@ def fdw_sparse_bind(g, name: str, coords: np.ndarray, nt: int, ddata: Optional[i
     out = ctypes.c_void_p()
     cp = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if npoint else None
     _chk(load().fdw_sparse_bind(g, name.encode(), npoint, nt, cp, ddata, ctypes.byref(out)))
+    return out.value
+
+
+def fdw_sparse_bind_precomputed(g, name: str, gridpoints: np.ndarray, coeffs: np.ndarray, nt: int,
+                                ddata: Optional[int]) -> int:
+    """gridpoints [npoint][ndim] first support index per axis, coeffs
+    [npoint][ndim][r] per-axis coefficients."""
+    gp = np.ascontiguousarray(gridpoints, dtype=np.int64)
+    cf = np.ascontiguousarray(coeffs, dtype=np.float64)
+    npoint = gp.shape[0] if gp.size else 0
+    r = cf.shape[-1] if cf.ndim == 3 else 0
+    if npoint and (cf.ndim != 3 or cf.shape[:2] != gp.shape):
+        raise ValueError(f"coeffs shape {cf.shape} does not match gridpoints {gp.shape}")
+    out = ctypes.c_void_p()
+    gptr = gp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if npoint else None
+    cptr = cf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if npoint else None
+    _chk(load().fdw_sparse_bind_precomputed(g, name.encode(), npoint, nt, r if npoint else 2, gptr, cptr, ddata,
+                                            ctypes.byref(out)))
     return out.value
 
 
@@ -306,12 +327,18 @@ class Shot:
             self.fn[nm] = fdw_function_bind(self.grid, nm, t.data_ptr(), E, prob.so)
         nt = prob.nt
         self.src_data = torch.from_numpy(np.ascontiguousarray(prob.src, dtype=np.float32)).to(self.device)
-        self.src = fdw_sparse_bind(self.grid, "src", prob.src_coords, nt,
-                                   self.src_data.data_ptr() if self.src_data.numel() else None)
+        src_ptr = self.src_data.data_ptr() if self.src_data.numel() else None
+        if getattr(prob, "src_pre", None) is not None:
+            self.src = fdw_sparse_bind_precomputed(self.grid, "src", *prob.src_pre, nt, src_ptr)
+        else:
+            self.src = fdw_sparse_bind(self.grid, "src", prob.src_coords, nt, src_ptr)
         nrec = prob.rec_coords.shape[0]
         self.rec_data = torch.zeros((nt, max(nrec, 0)), dtype=torch.float32, device=self.device)
-        self.rec = fdw_sparse_bind(self.grid, "rec", prob.rec_coords, nt,
-                                   self.rec_data.data_ptr() if nrec else None)
+        rec_ptr = self.rec_data.data_ptr() if nrec else None
+        if getattr(prob, "rec_pre", None) is not None:
+            self.rec = fdw_sparse_bind_precomputed(self.grid, "rec", *prob.rec_pre, nt, rec_ptr)
+        else:
+            self.rec = fdw_sparse_bind(self.grid, "rec", prob.rec_coords, nt, rec_ptr)
         d = fdw_op_desc()
         d.kind = kind
         d.space_order = prob.so

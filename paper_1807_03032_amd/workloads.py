@@ -105,6 +105,10 @@ class Problem:
     src: np.ndarray                # [nt][nsrc]
     rec_coords: np.ndarray         # [nrec][ndim]
     rc: float = 1e-3               # damping reflection coefficient
+    # precomputed sparse supports (gridpoints [n][ndim], coeffs [n][ndim][r]);
+    # when set they replace the linear weights of src_coords / rec_coords
+    src_pre: Optional[tuple] = None
+    rec_pre: Optional[tuple] = None
 
     @property
     def ndim(self):
@@ -261,3 +265,26 @@ def config_3d_iso_adjoint_320(nt: Optional[int] = None, n: int = 320):
     prob = Problem(f"3d_iso_adjoint_{n}cube_so8", "iso", shape, extent, (0.0,) * 3, 8, nbl, nt, dt, vmax, 0.0,
                    fields, src_coords, f32(src), rec_coords)
     return prob, m_true
+
+
+def lagrange_support(shape, spacing, origin, coords, r: int):
+    """Inputs of a precomputed sparse function with an r-point Lagrange scheme
+    per axis: for each point and axis, the first index of r consecutive grid
+    nodes around the point (shifted to stay inside the grid) and the r Lagrange
+    basis polynomials of those nodes evaluated at the point."""
+    c = np.asarray(coords, dtype=np.float64).reshape(-1, len(shape))
+    gp = np.zeros(c.shape, dtype=np.int64)
+    cf = np.zeros(c.shape + (r,))
+    for p in range(c.shape[0]):
+        for a in range(len(shape)):
+            xi = (c[p, a] - origin[a]) / spacing[a]
+            b = min(max(int(np.floor(xi)) - (r - 1) // 2, 0), shape[a] - r)
+            gp[p, a] = b
+            for j in range(r):
+                num, den = 1.0, 1.0
+                for k in range(r):
+                    if k != j:
+                        num *= xi - (b + k)
+                        den *= j - k
+                cf[p, a, j] = num / den
+    return gp, cf

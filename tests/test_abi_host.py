@@ -182,3 +182,22 @@ def test_binding_fails_loudly_without_library(tmp_path):
             mod.load(str(tmp_path / "missing.so"))
     finally:
         mod._lib = saved
+
+
+def test_precomputed_sparse_validation():
+    g = fdw.fdw_grid_create((12, 10, 9), (110.0, 90.0, 80.0))
+    fake = 0x7F0000000000
+    gp = np.array([[3, 2, 1]], dtype=np.int64)
+    with pytest.raises(fdw.FdwError) as e:
+        fdw.fdw_sparse_bind_precomputed(g, "s", gp, np.full((1, 3, 5), 0.2), 10, fake)  # r = 5 > max
+    assert e.value.code == fdw.FDW_ERR_ARG
+    with pytest.raises(fdw.FdwError) as e:
+        fdw.fdw_sparse_bind_precomputed(g, "s", np.array([[9, 2, 1]]), np.full((1, 3, 4), 0.25), 10, fake)
+    assert e.value.code == fdw.FDW_ERR_DOMAIN  # x support 9..12 leaves the 12-point axis
+    assert "outside" in fdw.fdw_last_error()
+    with pytest.raises(fdw.FdwError) as e:
+        fdw.fdw_sparse_bind_precomputed(g, "s", np.array([[0, -1, 1]]), np.full((1, 3, 2), 0.5), 10, fake)
+    assert e.value.code == fdw.FDW_ERR_DOMAIN
+    s = fdw.fdw_sparse_bind_precomputed(g, "s", np.array([[8, 6, 5]]), np.full((1, 3, 4), 0.25), 10, fake)
+    fdw.fdw_sparse_destroy(s)
+    fdw.fdw_grid_destroy(g)

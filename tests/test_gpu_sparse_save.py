@@ -1,0 +1,133 @@
+"""GPU parity of precomputed sparse functions (Section 3.3: custom
+interpolation given as grid points and coefficients) and of subsampled level
+saving (Section 3.5, ConditionalDimension with a factor, Listing fd-4), through
+the C ABI, against the FP64 oracle on identical seeded inputs.
+
+Bar: relative L2 <= 1e-4 per output (FP32 against FP64), as for the other
+parity tests; where two GPU paths must agree exactly the comparison is
+element-wise equality.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_03032_amd import workloads as W
+
+from test_gpu_parity import TOL, check, gpu_run, oracle_run, rel_l2, say, torch_dev  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_grid(prob):
+    return oracle.Grid(prob.shape, prob.extent, prob.origin, so=prob.so, dt=prob.dt, nbl=prob.nbl, vmax=prob.vmax,
+                       rc=prob.rc)
+
+
+def with_support(prob, r_src, r_rec):
+    """The problem with r-point Lagrange supports for its sources / receivers."""
+    sp = W.lagrange_support(prob.shape, prob.spacing, prob.origin, prob.src_coords, r_src) if r_src else None
+    rp = W.lagrange_support(prob.shape, prob.spacing, prob.origin, prob.rec_coords, r_rec) if r_rec else None
+    return dataclasses.replace(prob, src_pre=sp, rec_pre=rp)
+
+
+def oracle_run_pre(prob):
+    g = oracle_grid(prob)
+    sp = prob.src_pre
+    rp = prob.rec_pre
+    if sp is None:  # linear sources through the precomputed form of the same weights
+        sp = W.lagrange_support(prob.shape, prob.spacing, prob.origin, prob.src_coords, 2)
+    if rp is None:
+        rp = W.lagrange_support(prob.shape, prob.spacing, prob.origin, prob.rec_coords, 2)
+    up, uc, rec = oracle.iso_run_pre(g, prob.fields["m"], prob.nt, sp, prob.src, rp)
+    return {"u": (up, uc)}, rec
+
+
+@pytest.mark.parametrize("shape,so,r_src,r_rec", [((41, 36, 31), 8, 4, 4), ((37, 29, 23), 12, 3, 2),
+                                                  ((63, 51), 4, 4, 3), ((70, 44), 16, 1, 4)])
+def test_precomputed_supports(torch_dev, shape, so, r_src, r_rec):
+    """r-point Lagrange supports: non-linear weights, 1 to 64 support points,
+    the per-receiver sampling kernel and the scatter injection kernel."""
+    base = W.small_problem("iso", shape, so, nt=30, seed=60 + so, nsrc=3, nrec=40, nbl=4)
+    prob = with_support(base, r_src, r_rec)
+    say("precomputed", shape, so, r_src, r_rec)
+    gf, gtr, desc = gpu_run(prob, torch_dev)
+    of, otr = oracle_run_pre(prob)
+    check(prob, gf, gtr, of, otr)
+
+
+@pytest.mark.parametrize("shape", [(39, 33, 28), (57, 46)])
+def test_linear_precomputed_matches_linear_bind(torch_dev, shape):
+    """r = 2 with the linear coefficients takes the fused paths and gives the
+    same bits as the coordinate-based sparse function."""
+    base = W.small_problem("iso", shape, 8, nt=25, seed=77, nsrc=2, nrec=30, nbl=4)
+    g = oracle_grid(base)
+
+    def linear(coords):
+        c = np.asarray(coords, dtype=np.float64).reshape(-1, base.ndim)
+        gp = np.zeros(c.shape, dtype=np.int64)
+        cf = np.zeros(c.shape + (2,))
+        for p in range(c.shape[0]):
+            for a in range(base.ndim):
+                xi = (c[p, a] - g.origin[a]) / g.spacing[a]
+                b = min(int(np.floor(xi)), base.shape[a] - 2)
+                gp[p, a] = b
+                cf[p, a] = (1.0 - (xi - b), xi - b)
+        return gp, cf
+
+    pre = dataclasses.replace(base, src_pre=linear(base.src_coords), rec_pre=linear(base.rec_coords))
+    say("linear precomputed", shape)
+    f1, t1, d1 = gpu_run(base, torch_dev)
+    f2, t2, d2 = gpu_run(pre, torch_dev)
+    assert d1 == d2
+    np.testing.assert_array_equal(f1["u"][1], f2["u"][1])
+    np.testing.assert_array_equal(t1, t2)
+
+
+# ------------------------------------------------------- subsampled saving
+def oracle_levels(prob):
+    """Levels 0..nt of the isotropic run, one oracle step at a time."""
+    g = oracle_grid(prob)
+    up = np.zeros(prob.array_shape)
+    uc = np.zeros(prob.array_shape)
+    levels = [uc.copy()]
+    for t in range(prob.nt):
+        up, uc, _ = oracle.iso_run(g, prob.fields["m"], prob.nt, up, uc, src_coords=prob.src_coords, src=prob.src,
+                                   rec_coords=None, time_m=t, time_M=t)
+        levels.append(uc.copy())
+    return levels
+
+
+@pytest.mark.parametrize("shape,nsrc,every,first,nlevels,nslots",
+                         [((37, 31, 26), 1, 4, 1, 6, 3),    # fused store in the stencil kernel
+                          ((37, 31, 26), 6, 4, 3, 5, 3),    # scatter injection: copy after the step
+                          ((33, 29, 24), 1, 3, 2, 4, 2),    # in-place two-slot storage
+                          ((61, 47), 2, 5, 0, 5, 3)])       # 2D (per-step kernel while saving)
+def test_subsampled_save(torch_dev, shape, nsrc, every, first, nlevels, nslots):
+    import torch
+
+    from paper_1807_03032_amd import fdw
+
+    prob = W.small_problem("iso", shape, 8, nt=22, seed=90 + nsrc, nsrc=nsrc, nrec=5, nbl=4)
+    say("save", shape, nsrc, every, first, nlevels, nslots)
+    shot = fdw.Shot(prob, torch_dev, nslots=nslots)
+    try:
+        E = shot.lay.elems_per_slot
+        # one slot more than asked for, filled with a sentinel: never written
+        buf = torch.full(((nlevels + 1) * E,), 7.0, dtype=torch.float32, device=torch_dev)
+        fdw.fdw_operator_set_save(shot.op, buf.data_ptr(), nlevels, every, first)
+        shot.apply(0, prob.nt - 1)
+        torch.cuda.synchronize()
+        got = [fdw.download(buf, shot.lay, k) for k in range(nlevels + 1)]
+    finally:
+        shot.close()
+    ref = oracle_levels(prob)
+    saved = [L for L in range(first, prob.nt + 1, every)][:nlevels]
+    assert len(saved) == nlevels
+    for k, L in enumerate(saved):
+        e = rel_l2(got[k], ref[L])
+        say("level", L, "slot", k, f"{e:.2e}")
+        assert np.linalg.norm(ref[L]) > 0 or L == 0
+        assert e <= TOL, (L, e)
+    assert np.all(got[nlevels] == 7.0)
