@@ -236,6 +236,101 @@ int fdw_gradient_accumulate(fdw_op *op, const float *nu, const float *u_next, co
 int fdw_sync(fdw_op *op);
 int fdw_operator_destroy(fdw_op *op);
 
+/* ---------------------------------------------------------------------------
+ * Fused multi-shot steps.  fdw_batch_apply advances n operators of the same
+ * kind, space order and grid shape (distinct wavefields, models, sources and
+ * receivers) over their own step ranges time_m[i]..time_M[i] with one launch
+ * per stage and step for all of them (the shot index is a grid dimension);
+ * shots with shorter ranges sit out the later launches.  Each shot's results
+ * are those of fdw_operator_apply over the same range with the same kernels
+ * (bit for bit in 3D and for 2D grids too large for the LDS-resident kernel).
+ * Restrictions: forward mode, no level saving, at most 4 sources with linear
+ * weights (fused injection), receivers with linear weights, 3D operators on
+ * the streaming kernels.  A batch object owns pinned and device buffers for
+ * the per-shot records of one call; on a stream other than the null stream
+ * the call's launch sequence is captured in a hipGraph, kept, and replayed by
+ * later calls with the same shot count, step count and receiver width.
+ * Calls on one batch object are ordered on their stream; the object may be
+ * reused immediately (the record upload of the previous call is awaited).
+ * Errors: FDW_ERR_ARG (mismatch, restriction, range), FDW_ERR_NOMEM,
+ * FDW_ERR_DEVICE. */
+typedef struct fdw_batch fdw_batch;
+int fdw_batch_create(fdw_batch **out);
+int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, const int *time_M, void *stream);
+int fdw_batch_stats(const fdw_batch *b, int64_t *graph_builds, int64_t *graph_launches);
+int fdw_batch_destroy(fdw_batch *b);
+
+/* ---------------------------------------------------------------------------
+ * Shot server: continuous batching of forward-modelling requests on one GPU.
+ * Requests (kind, grid, space order, step count, model, sources, receivers)
+ * are queued by fdw_server_submit.  Each fdw_server_progress call is one
+ * non-blocking scheduling round: it retires shots whose work has completed
+ * (receiver traces already copied to host memory), admits queued requests in
+ * arrival order while their device footprint fits in the budget left (later
+ * requests may pass one that does not fit), and enqueues the next chunk of
+ * steps of every bucket of running shots -- shots of one kind, grid and space
+ * order -- as fused multi-shot launches (fdw_batch_apply, replayed hipGraphs),
+ * each bucket on one of nstreams streams so that buckets overlap on the
+ * device.  Shots join and leave their bucket between chunks; chunk length
+ * aims at chunk_target_us of device time (0: 20 ms).
+ * Ownership: the host arrays a description points to are borrowed until the
+ * shot is admitted (fdw_server_info state RUNNING or DONE); the server owns
+ * all device memory (wavefields in two-slot in-place storage).  budget_bytes
+ * <= 0 selects 80 % of the free device memory.  Single-threaded: calls on one
+ * server must not overlap.
+ * Errors: FDW_ERR_ARG, FDW_ERR_NOMEM (footprint above the budget at submit,
+ * or allocation), FDW_ERR_STATE (fetch before completion), FDW_ERR_DEVICE,
+ * and the operator-creation errors of a request (at its admission). */
+#define FDW_SHOT_QUEUED 0
+#define FDW_SHOT_RUNNING 1
+#define FDW_SHOT_DONE 2
+
+typedef struct {
+    int kind;                  /* FDW_ISO or FDW_TTI                                     */
+    int ndim;                  /* 2 or 3                                                 */
+    int64_t shape[3];          /* as fdw_grid_create                                     */
+    double extent[3], origin[3];
+    int space_order;           /* even, 2..16                                            */
+    int nt;                    /* steps 0..nt-1                                          */
+    double dt;
+    int nbl;
+    double damp_rc, vmax, eps_max;
+    const float *m;            /* host logical arrays, x fastest (numpy order reversed)  */
+    const float *eps, *delta, *theta, *phi;  /* TTI (phi 3D only); NULL for ISO          */
+    int nsrc;                  /* 0..4                                                   */
+    const double *src_coords;  /* [nsrc][ndim]                                           */
+    const float *src;          /* [nt][nsrc]                                             */
+    int nrec;
+    const double *rec_coords;  /* [nrec][ndim]                                           */
+    int keep_field;            /* 1: keep the last level of u (p) for fdw_server_fetch   */
+} fdw_shot_desc;
+
+typedef struct {
+    int state;                 /* FDW_SHOT_QUEUED / RUNNING / DONE                       */
+    int steps_done;
+    int64_t footprint;         /* device bytes held while running                        */
+    double t_submit, t_admit, t_done;  /* seconds on the server's clock                  */
+} fdw_shot_info;
+
+typedef struct {
+    int64_t budget, used, pool_bytes;  /* bytes                                          */
+    int64_t chunks, admitted, completed, buckets;
+    int64_t graph_builds, graph_launches;
+    double now;                /* the server's clock (seconds since creation)            */
+} fdw_server_stats_t;
+
+typedef struct fdw_server fdw_server;
+int fdw_server_create(int64_t budget_bytes, int chunk_target_us, int nstreams, fdw_server **out);
+int fdw_server_footprint(const fdw_shot_desc *d, int64_t *bytes);  /* host only */
+int fdw_server_submit(fdw_server *sv, const fdw_shot_desc *d, int64_t *ticket);
+int fdw_server_progress(fdw_server *sv, int *queued, int *running);
+int fdw_server_info(fdw_server *sv, int64_t ticket, fdw_shot_info *out);
+/* rec_host [nt][nrec] and/or field_host (logical last level) of a DONE shot */
+int fdw_server_fetch(fdw_server *sv, int64_t ticket, float *rec_host, float *field_host);
+int fdw_server_release(fdw_server *sv, int64_t ticket);
+int fdw_server_stats(fdw_server *sv, fdw_server_stats_t *out);
+int fdw_server_destroy(fdw_server *sv);
+
 /* Per-kernel timing (measurement support).  enable = k > 0 brackets one launch
  * in every k of the operator's dominant stencil kernel (counting from the first
  * launch after this call; k = 1: every launch) with a pair of HIP events on the

@@ -10,6 +10,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 namespace fdw {
@@ -206,21 +207,23 @@ struct StreamPoint {
 };
 
 template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
-__global__ void __launch_bounds__(64 * BY) stream3d(Op op, StreamFields<NQ, NP> F, Geom g, int zc, int ntx, int nty,
-                                                   int zfast, SparseArgs sp, int nb_stencil) {
+__device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc,
+                                              int ntx, int nty, int zfast, const SparseArgs &sp, int nb_stencil,
+                                              int bid, bool stencil_live) {
     constexpr int NT = 64 * BY;  // threads per workgroup
     // workgroups past the stencil tiles sample the receivers of the previous
     // step from the current level, which this launch only reads
-    if ((int)blockIdx.x >= nb_stencil) {
-        interp_lane(sp, ((int)blockIdx.x - nb_stencil) * NT + (int)threadIdx.x);
+    if (bid >= nb_stencil) {
+        interp_lane(sp, (bid - nb_stencil) * NT + (int)threadIdx.x);
         return;
     }
+    if (!stencil_live) return;
     constexpr int TX = 64, TY = BY * NY, LW = TX + 2 * R, LH = TY + 2 * R, Q = 2 * R + 1;
     constexpr int NHY = (2 * R + BY - 1) / BY;       // y-halo rows per wavefront
     constexpr int NHX = (TY * 2 * R + NT - 1) / NT;  // x-halo elements per thread
     __shared__ float lds[2][NQ][LH][LW];
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-    int tile = xcd_tile(blockIdx.x, nb_stencil);
+    int tile = xcd_tile(bid, nb_stencil);
     int tx, ty, tz;
     if (zfast) {  // z-chunk fastest: every chunk of a column on one XCD
         const int ntz = (g.nz + zc - 1) / zc;
@@ -386,6 +389,47 @@ __global__ void __launch_bounds__(64 * BY) stream3d(Op op, StreamFields<NQ, NP> 
         run(std::integral_constant<int, -1>{});
     else
         run(std::integral_constant<int, 1>{});
+}
+
+template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
+__global__ void __launch_bounds__(64 * BY) stream3d(Op op, StreamFields<NQ, NP> F, Geom g, int zc, int ntx, int nty,
+                                                   int zfast, SparseArgs sp, int nb_stencil) {
+    stream3d_body<R, NY, PF, NQ, NP, BY>(op, F, g, zc, ntx, nty, zfast, sp, nb_stencil, (int)blockIdx.x, true);
+}
+
+// One shot's share of a fused multi-shot launch: its operator and fields for
+// this step, the receiver row it samples (npoint = 0: none), and whether its
+// stencil runs (a shot whose range has ended only samples its last row).
+template <class Op, int NQ, int NP>
+struct StreamShot {
+    Op op;
+    StreamFields<NQ, NP> F;
+    SparseArgs rec;
+    int live;
+};
+
+// Same-geometry shots in one launch: blockIdx.y selects the shot.
+template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
+__global__ void __launch_bounds__(64 * BY) stream3d_multi(const StreamShot<Op, NQ, NP> *__restrict__ shots, Geom g,
+                                                         int zc, int ntx, int nty, int zfast, int nb_stencil) {
+    const StreamShot<Op, NQ, NP> &S = shots[blockIdx.y];
+    stream3d_body<R, NY, PF, NQ, NP, BY>(S.op, S.F, g, zc, ntx, nty, zfast, S.rec, nb_stencil, (int)blockIdx.x,
+                                         S.live != 0);
+}
+
+// Fused launch of n same-geometry shots (records in device memory); rec_lanes
+// = the largest npoint * ncorner of the shots' receiver rows.
+template <int R, int NY, int PF, int BY, int NQ, int NP, class Op>
+static hipError_t launch_stream3d_multi(const StreamShot<Op, NQ, NP> *shots, int n, int64_t rec_lanes, const Geom &g,
+                                        int zc, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (zc > g.nz) zc = g.nz;
+    const int ntx = (g.nx + 63) / 64, nty = (g.ny + BY * NY - 1) / (BY * NY), ntz = (g.nz + zc - 1) / zc;
+    const int64_t nb = (int64_t)ntx * nty * ntz;
+    const int64_t ni = (rec_lanes + 64 * BY - 1) / (64 * BY);
+    hipLaunchKernelGGL((stream3d_multi<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)(nb + ni), (unsigned)n),
+                       dim3(64 * BY), 0, s, shots, g, zc, ntx, nty, 0, (int)nb);
+    return hipGetLastError();
 }
 
 // Does any fused source's interpolation cell touch the box

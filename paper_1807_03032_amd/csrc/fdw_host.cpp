@@ -38,6 +38,11 @@ static int fail(int code, const char *fmt, ...) {
     return code;
 }
 
+int fdw::set_error(int code, const char *msg) {
+    g_last_error = msg;
+    return code;
+}
+
 static int fail_hip(hipError_t e, const char *where) {
     return fail(FDW_ERR_DEVICE, "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
 }
@@ -693,7 +698,8 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
                                  tf->d + (int64_t)sl * L.elems_per_slot, nullptr);
             if (e != hipSuccess) break;
         }
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    // the null stream only: work of the caller's other streams is not waited for
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         release_device(op);
         delete op;
@@ -751,6 +757,96 @@ int fdw_operator_destroy(fdw_op *op) {
     return FDW_OK;
 }
 
+// Injection / interpolation argument templates of an operator (field, row
+// and sample pointers are filled per step).
+static SparseArgs sparse_template(const fdw_op *op, const fdw_sparse *sp, bool rec) {
+    const fdw_op_desc &d = op->d;
+    SparseArgs a{};
+    a.ndim = op->ndim;
+    a.eta_x = op->d_eta;
+    a.eta_y = op->d_eta + op->geom.nx;
+    a.eta_z = op->d_eta + op->geom.nx + op->geom.ny;
+    a.npoint = sp ? sp->npoint : 0;
+    a.r = sp ? sp->r : 2;
+    a.ncorner = sp ? sp->ncorner : 1 << op->ndim;
+    a.cstride[0] = 1;
+    a.cstride[1] = op->ndim == 3 ? op->geom.sy : op->geom.sz;
+    a.cstride[2] = op->ndim == 3 ? op->geom.sz : 0;
+    if (rec) {
+        a.damp_mode = d.mode == FDW_ADJOINT ? 2 : 0;
+        a.idx = op->d_rec_idx;
+        a.base = op->d_rec_base;
+        a.w = op->d_rec_w;
+        a.m = nullptr;
+    } else {
+        a.damp_mode = d.mode == FDW_ADJOINT ? 1 : 0;
+        a.idx = op->d_src_idx;
+        a.base = op->d_src_base;
+        a.w = op->d_src_w;
+        a.m = d.m->d;
+    }
+    return a;
+}
+
+// Stencil arguments of step t (level t + 1 from levels t and t - 1; level k
+// in slot k mod nslots, so with two slots the new level overwrites t - 1).
+static void iso_step_args(const fdw_op *op, int t, IsoArgs &a) {
+    const fdw_op_desc &d = op->d;
+    const int64_t E = op->lay.elems_per_slot;
+    const int S = d.u->nslots;
+    const int sc = t % S, sp = (t + S - 1) % S, sn = (t + 1) % S;
+    a = IsoArgs{};
+    a.g = op->geom;
+    a.u_cur = d.u->d + sc * E;
+    a.u_prev = d.u->d + sp * E;
+    a.u_next = d.u->d + sn * E;
+    a.m = d.m->d;
+    a.eta_x = op->d_eta;
+    a.eta_y = op->d_eta + op->geom.nx;
+    a.eta_z = op->d_eta + op->geom.nx + op->geom.ny;
+    a.dt2 = op->dt2;
+    a.c = op->coefs;
+    if (op->src_fused && d.src && d.src->npoint > 0) {
+        a.src = op->fsrc_template;
+        a.src.q = d.src->data + (int64_t)t * d.src->npoint;
+    }
+    a.adjoint = d.mode == FDW_ADJOINT;
+    a.save = nullptr;
+    a.rec = nullptr;
+}
+
+static void tti_step_args(const fdw_op *op, int t, TtiArgs &a) {
+    const fdw_op_desc &d = op->d;
+    const int64_t E = op->lay.elems_per_slot;
+    const int S = d.u->nslots;
+    const int sc = t % S, sp = (t + S - 1) % S, sn = (t + 1) % S;
+    a = TtiArgs{};
+    a.g = op->geom;
+    a.p_cur = d.u->d + sc * E;
+    a.p_prev = d.u->d + sp * E;
+    a.p_next = d.u->d + sn * E;
+    a.r_cur = d.r->d + sc * E;
+    a.r_prev = d.r->d + sp * E;
+    a.r_next = d.r->d + sn * E;
+    a.m = d.m->d;
+    a.eps = d.eps->d;
+    a.delta = d.delta->d;
+    a.theta = d.theta->d;
+    a.phi = d.phi ? d.phi->d : nullptr;
+    a.gp = op->d_stage;
+    a.gr = op->d_stage + E;
+    a.eta_x = op->d_eta;
+    a.eta_y = op->d_eta + op->geom.nx;
+    a.eta_z = op->d_eta + op->geom.nx + op->geom.ny;
+    a.dt2 = op->dt2;
+    a.c = op->coefs;
+    if (op->src_fused && d.src && d.src->npoint > 0) {
+        a.src = op->fsrc_template;
+        a.src.q = d.src->data + (int64_t)t * d.src->npoint;
+    }
+    a.rec = nullptr;
+}
+
 static int timing_event_pair(fdw_op *op, hipEvent_t *a, hipEvent_t *b) {
     while (op->ev_used + 2 > op->ev_pool.size()) {
         hipEvent_t e;
@@ -784,36 +880,13 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         return fail(FDW_ERR_ARG, "operator_apply: time_M = %d beyond the %d receiver samples", time_M, d.rec->nt);
     const fdw_layout &L = op->lay;
     const int64_t E = L.elems_per_slot;
-    const float *eta_x = op->d_eta, *eta_y = op->d_eta + op->geom.nx, *eta_z = op->d_eta + op->geom.nx + op->geom.ny;
+    const float *eta_x = op->d_eta, *eta_z = op->d_eta + op->geom.nx + op->geom.ny;
     const int nsrc = d.src ? d.src->npoint : 0;
     const int nrec = d.rec ? d.rec->npoint : 0;
     if (op->timing) op->last_stream = s;
 
-    SparseArgs inj{};
-    inj.ndim = op->ndim;
-    inj.eta_x = eta_x;
-    inj.eta_y = eta_y;
-    inj.eta_z = eta_z;
-    inj.damp_mode = d.mode == FDW_ADJOINT ? 1 : 0;
-    inj.idx = op->d_src_idx;
-    inj.npoint = nsrc;
-    inj.r = d.src ? d.src->r : 2;
-    inj.ncorner = d.src ? d.src->ncorner : 1 << op->ndim;
-    inj.base = op->d_src_base;
-    inj.w = op->d_src_w;
-    inj.cstride[0] = 1;
-    inj.cstride[1] = op->ndim == 3 ? op->geom.sy : op->geom.sz;
-    inj.cstride[2] = op->ndim == 3 ? op->geom.sz : 0;
-    inj.m = d.m->d;
-    SparseArgs itp = inj;
-    itp.npoint = nrec;
-    itp.r = d.rec ? d.rec->r : 2;
-    itp.ncorner = d.rec ? d.rec->ncorner : 1 << op->ndim;
-    itp.base = op->d_rec_base;
-    itp.w = op->d_rec_w;
-    itp.m = nullptr;
-    itp.damp_mode = d.mode == FDW_ADJOINT ? 2 : 0;
-    itp.idx = op->d_rec_idx;
+    SparseArgs inj = sparse_template(op, d.src, false);
+    SparseArgs itp = sparse_template(op, d.rec, true);
 
     // small 2D isotropic grids: the whole range in one persistent launch
     if (d.kind == FDW_ISO && op->ndim == 2 && op->use_persist2d && !op->save_buf && time_M >= time_m) {
@@ -869,14 +942,7 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             hipError_t er = hipStreamWaitEvent(s, op->ev_interp[(t - d.u->nslots) % S_ring], 0);
             if (er != hipSuccess) return fail_hip(er, "operator_apply: hipStreamWaitEvent");
         }
-        // level k lives in slot k mod S; with S = 2 the new level overwrites t - 1
-        const int S = d.u->nslots;
-        const int sc = t % S, sp = (t + S - 1) % S, sn = (t + 1) % S;
-        FusedSrc fs{};
-        if (op->src_fused && nsrc > 0) {
-            fs = op->fsrc_template;
-            fs.q = d.src->data + (int64_t)t * nsrc;
-        }
+        const int sn = (t + 1) % d.u->nslots;
         LaunchEvents ev;
         const bool timed = op->timing && op->timing_seq++ % op->timing_every == 0;
         if (timed) {
@@ -887,20 +953,8 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         float *next_field;
         float *save_dst = nullptr;
         if (d.kind == FDW_ISO) {
-            IsoArgs a{};
-            a.g = op->geom;
-            a.u_cur = d.u->d + sc * E;
-            a.u_prev = d.u->d + sp * E;
-            a.u_next = d.u->d + sn * E;
-            a.m = d.m->d;
-            a.eta_x = eta_x;
-            a.eta_y = eta_y;
-            a.eta_z = eta_z;
-            a.dt2 = op->dt2;
-            a.c = op->coefs;
-            a.src = fs;
-            a.adjoint = d.mode == FDW_ADJOINT;
-            a.save = nullptr;
+            IsoArgs a;
+            iso_step_args(op, t, a);
             SparseArgs prev_itp = itp;
             a.rec = nullptr;
             if (fuse_interp && t > time_m) {
@@ -917,27 +971,8 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             e = launch_iso(op->ndim, op->R, op->iso_v, a, s, ev);
             next_field = a.u_next;
         } else {
-            TtiArgs a{};
-            a.g = op->geom;
-            a.p_cur = d.u->d + sc * E;
-            a.p_prev = d.u->d + sp * E;
-            a.p_next = d.u->d + sn * E;
-            a.r_cur = d.r->d + sc * E;
-            a.r_prev = d.r->d + sp * E;
-            a.r_next = d.r->d + sn * E;
-            a.m = d.m->d;
-            a.eps = d.eps->d;
-            a.delta = d.delta->d;
-            a.theta = d.theta->d;
-            a.phi = d.phi ? d.phi->d : nullptr;
-            a.gp = op->d_stage;
-            a.gr = op->d_stage + E;
-            a.eta_x = eta_x;
-            a.eta_y = eta_y;
-            a.eta_z = eta_z;
-            a.dt2 = op->dt2;
-            a.c = op->coefs;
-            a.src = fs;
+            TtiArgs a;
+            tti_step_args(op, t, a);
             SparseArgs prev_itp = itp;
             a.rec = nullptr;
             if (fuse_interp && t > time_m) {
@@ -1077,6 +1112,247 @@ int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_b
     // and writes p, r.
     if (alg_bytes_per_point)
         *alg_bytes_per_point = iso ? 16.0 : (op->ndim == 3 ? 44.0 : 40.0);
+    return FDW_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Fused multi-shot steps: several operators of one geometry advance together,
+// one launch per stage and step for all of them (shot index as a grid
+// dimension).  Per-shot, per-step records are packed on the host into a pinned
+// buffer, copied to the device once per call, and the launch sequence of a
+// call is captured once in a hipGraph and replayed while the shot count,
+// step count and receiver width stay the same.
+// ---------------------------------------------------------------------------
+struct fdw_batch {
+    char *h_stage = nullptr;  // pinned host records
+    char *d_stage = nullptr;  // device records
+    size_t cap = 0;
+    hipEvent_t ev_copy = nullptr;
+    bool copy_pending = false;
+    // cached graph of the last launch sequence
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int64_t> key;
+    hipStream_t graph_stream = nullptr;
+    int64_t graph_replays = 0, graph_builds = 0;
+};
+
+static void batch_drop_graph(fdw_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->key.clear();
+}
+
+static size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+extern "C" {
+
+int fdw_batch_create(fdw_batch **out) {
+    FDW_GUARD_BEGIN
+    if (!out) return fail(FDW_ERR_ARG, "batch_create: NULL out");
+    fdw_batch *b = new fdw_batch();
+    hipError_t e = hipEventCreateWithFlags(&b->ev_copy, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete b;
+        return fail_hip(e, "batch_create: hipEventCreate");
+    }
+    *out = b;
+    return FDW_OK;
+    FDW_GUARD_END
+}
+
+int fdw_batch_destroy(fdw_batch *b) {
+    if (!b) return FDW_OK;
+    if (b->copy_pending) (void)hipEventSynchronize(b->ev_copy);
+    batch_drop_graph(b);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    if (b->d_stage) (void)hipFree(b->d_stage);
+    if (b->ev_copy) (void)hipEventDestroy(b->ev_copy);
+    delete b;
+    return FDW_OK;
+}
+
+int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, const int *time_M, void *stream) {
+    FDW_GUARD_BEGIN
+    if (!b || !ops || !time_m || !time_M || n < 1) return fail(FDW_ERR_ARG, "batch_apply: NULL argument or n < 1");
+    const fdw_op *o0 = ops[0];
+    if (!o0) return fail(FDW_ERR_ARG, "batch_apply: NULL op");
+    const int kind = o0->d.kind, ndim = o0->ndim, R = o0->R;
+    int K = 0;
+    int64_t lanes = 0;
+    for (int i = 0; i < n; ++i) {
+        const fdw_op *op = ops[i];
+        if (!op) return fail(FDW_ERR_ARG, "batch_apply: NULL op %d", i);
+        const fdw_op_desc &d = op->d;
+        const Geom &g = op->geom, &g0 = o0->geom;
+        if (d.kind != kind || op->ndim != ndim || op->R != R || g.nx != g0.nx || g.ny != g0.ny || g.nz != g0.nz ||
+            g.sy != g0.sy || g.sz != g0.sz || g.off0 != g0.off0)
+            return fail(FDW_ERR_ARG, "batch_apply: op %d differs from op 0 in kind, space order or geometry", i);
+        if (d.mode != FDW_FORWARD || op->save_buf)
+            return fail(FDW_ERR_ARG, "batch_apply: op %d: forward operators without level saving only", i);
+        if (ndim == 3 && (kind == FDW_ISO ? op->iso_v != IsoVariant::Stream : op->tti_v != TtiVariant::Stream))
+            return fail(FDW_ERR_ARG, "batch_apply: op %d: 3D operators need the streaming kernels", i);
+        const int nsrc = d.src ? d.src->npoint : 0, nrec = d.rec ? d.rec->npoint : 0;
+        if (nsrc > 0 && !op->src_fused)
+            return fail(FDW_ERR_ARG, "batch_apply: op %d: at most %d sources with linear weights per shot", i,
+                        kMaxFusedSrc);
+        if (nrec > 0 && (d.rec->r != 2))
+            return fail(FDW_ERR_ARG, "batch_apply: op %d: receivers need linear weights", i);
+        if (time_m[i] < 0 || time_M[i] < time_m[i] - 1)
+            return fail(FDW_ERR_ARG, "batch_apply: op %d: invalid range %d..%d", i, time_m[i], time_M[i]);
+        if ((nsrc > 0 && time_M[i] >= d.src->nt) || (nrec > 0 && time_M[i] >= d.rec->nt))
+            return fail(FDW_ERR_ARG, "batch_apply: op %d: time_M = %d beyond the sparse time axis", i, time_M[i]);
+        K = std::max(K, time_M[i] - time_m[i] + 1);
+        lanes = std::max(lanes, (int64_t)nrec * (1 << ndim));
+    }
+    if (K == 0) return FDW_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // 3D: receivers of step t are sampled in the launch of step t + 1, so one
+    // more launch samples the last step; 2D: a sampling launch after each step
+    const int nl = (ndim == 3 && lanes > 0) ? K + 1 : K;
+    const size_t r1 = kind == FDW_ISO ? iso_multi_record_bytes(ndim) : tti_multi_record_bytes(ndim, 1);
+    const size_t r2 = (kind == FDW_TTI && ndim == 3) ? tti_multi_record_bytes(3, 2) : 0;
+    const size_t rs = ndim == 2 ? sizeof(SparseArgs) : 0;
+    const size_t off2 = align256(r1 * n), offs = off2 + align256(r2 * n);
+    const size_t step_bytes = offs + align256(rs * n);
+    const size_t total = step_bytes * (size_t)nl;
+    if (b->copy_pending) {
+        hipError_t e = hipEventSynchronize(b->ev_copy);
+        if (e != hipSuccess) return fail_hip(e, "batch_apply: waiting for the previous record copy");
+        b->copy_pending = false;
+    }
+    if (total > b->cap) {
+        // the device buffer may still be read by launched work on its stream
+        if (b->d_stage) {
+            hipError_t e = hipStreamSynchronize(b->graph_stream ? b->graph_stream : s);
+            if (e != hipSuccess) return fail_hip(e, "batch_apply: hipStreamSynchronize");
+        }
+        batch_drop_graph(b);
+        if (b->h_stage) (void)hipHostFree(b->h_stage);
+        if (b->d_stage) (void)hipFree(b->d_stage);
+        b->h_stage = b->d_stage = nullptr;
+        b->cap = 0;
+        const size_t cap = std::max(total, (size_t)1 << 20);
+        hipError_t e = hipHostMalloc((void **)&b->h_stage, cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void **)&b->d_stage, cap);
+        if (e != hipSuccess) return fail(FDW_ERR_NOMEM, "batch_apply: record buffers: %s", hipGetErrorString(e));
+        b->cap = cap;
+    }
+    // pack the records of every launch
+    std::memset(b->h_stage, 0, total);
+    for (int k = 0; k < nl; ++k) {
+        char *base = b->h_stage + (size_t)k * step_bytes;
+        for (int i = 0; i < n; ++i) {
+            const fdw_op *op = ops[i];
+            const fdw_op_desc &d = op->d;
+            const int cnt = time_M[i] - time_m[i] + 1;
+            const int t = time_m[i] + std::min(k, std::max(cnt - 1, 0));
+            const bool live = k < cnt;
+            const int nrec = d.rec ? d.rec->npoint : 0;
+            const int64_t E = op->lay.elems_per_slot;
+            const int S = d.u->nslots;
+            SparseArgs rec{};
+            if (nrec > 0) {
+                rec = sparse_template(op, d.rec, true);
+                if (ndim == 3) {
+                    // launch k samples row t - 1 from level t = time_m + k (its slot is
+                    // read-only in that launch)
+                    if (k >= 1 && k <= cnt) {
+                        const int lv = time_m[i] + k;
+                        rec.field = d.u->d + (int64_t)(lv % S) * E;
+                        rec.rec_row = d.rec->data + (int64_t)(lv - 1) * nrec;
+                    } else {
+                        rec.npoint = 0;
+                    }
+                } else {
+                    if (live) {
+                        rec.field = d.u->d + (int64_t)((t + 1) % S) * E;
+                        rec.rec_row = d.rec->data + (int64_t)t * nrec;
+                    } else {
+                        rec.npoint = 0;
+                    }
+                }
+            }
+            const SparseArgs none{};
+            if (kind == FDW_ISO) {
+                IsoArgs a;
+                iso_step_args(op, t, a);
+                multi_pack_iso(ndim, a, live, ndim == 3 ? rec : none, base + r1 * i);
+            } else {
+                TtiArgs a;
+                tti_step_args(op, t, a);
+                multi_pack_tti(ndim, a, live, ndim == 3 ? rec : none, base + r1 * i, r2 ? base + off2 + r2 * i : nullptr);
+            }
+            if (ndim == 2) std::memcpy(base + offs + rs * i, &rec, sizeof(rec));
+        }
+    }
+    hipError_t e = hipMemcpyAsync(b->d_stage, b->h_stage, total, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_copy, s);
+    if (e != hipSuccess) return fail_hip(e, "batch_apply: record upload");
+    b->copy_pending = true;
+
+    auto launches = [&](hipStream_t st) -> hipError_t {
+        for (int k = 0; k < nl; ++k) {
+            const char *base = b->d_stage + (size_t)k * step_bytes;
+            const int64_t rl = ndim == 3 ? lanes : 0;
+            hipError_t er = kind == FDW_ISO ? launch_iso_multi(ndim, R, o0->geom, base, n, rl, st)
+                                            : launch_tti_multi(ndim, R, o0->geom, base, r2 ? base + off2 : nullptr, n,
+                                                               rl, st);
+            if (er != hipSuccess) return er;
+            if (ndim == 2 && lanes > 0) {
+                er = launch_interp_multi(reinterpret_cast<const SparseArgs *>(base + offs), n, lanes, st);
+                if (er != hipSuccess) return er;
+            }
+        }
+        return hipSuccess;
+    };
+    const char *g_env = std::getenv("FDW_BATCH_GRAPH");
+    const bool use_graph = s != nullptr && !(g_env && g_env[0] == '0');
+    if (!use_graph) {
+        e = launches(s);
+        if (e != hipSuccess) return fail_hip(e, "batch_apply: launch");
+        return FDW_OK;
+    }
+    const std::vector<int64_t> key = {kind, ndim, R, o0->geom.nx, o0->geom.ny, o0->geom.nz, o0->geom.sy, o0->geom.sz,
+                                      o0->geom.off0, n, nl, lanes, (int64_t)step_bytes, (int64_t)(intptr_t)b->d_stage,
+                                      (int64_t)(intptr_t)s};
+    if (!b->exec || key != b->key) {
+        batch_drop_graph(b);
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail_hip(e, "batch_apply: hipStreamBeginCapture");
+        hipError_t el = launches(s);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s, &g);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail_hip(el != hipSuccess ? el : e, "batch_apply: graph capture");
+        }
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            b->exec = nullptr;
+            return fail_hip(e, "batch_apply: hipGraphInstantiate");
+        }
+        b->graph = g;
+        b->key = key;
+        b->graph_stream = s;
+        b->graph_builds++;
+    }
+    e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) return fail_hip(e, "batch_apply: hipGraphLaunch");
+    b->graph_replays++;
+    return FDW_OK;
+    FDW_GUARD_END
+}
+
+int fdw_batch_stats(const fdw_batch *b, int64_t *graph_builds, int64_t *graph_launches) {
+    if (!b) return fail(FDW_ERR_ARG, "batch_stats: NULL batch");
+    if (graph_builds) *graph_builds = b->graph_builds;
+    if (graph_launches) *graph_launches = b->graph_replays;
     return FDW_OK;
 }
 

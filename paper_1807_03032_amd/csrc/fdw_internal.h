@@ -88,6 +88,32 @@ struct SparseArgs {
     float *rec_row;              // interpolation: output row of this step
 };
 
+// One shot of a fused multi-shot launch of the one-thread-per-point kernels.
+template <class A>
+struct NaiveShot {
+    A a;
+    int live;
+};
+
+// ---- fused multi-shot steps (same geometry, space order and kind) ----------
+// The host packs one record per shot and step (multi_pack_*), the caller
+// uploads the records, and one launch per stage runs every shot.  3D steps
+// sample the receiver row `rec` inside the stencil launch; 2D steps sample it
+// with launch_interp_multi after the step.  live = 0: the shot's stencil is
+// skipped (its receiver row, if any, is still sampled).
+// sets the thread-local message fdw_last_error returns; returns code
+int set_error(int code, const char *msg);
+
+size_t iso_multi_record_bytes(int ndim);
+size_t tti_multi_record_bytes(int ndim, int stage);  // stage 1 or 2
+void multi_pack_iso(int ndim, const IsoArgs &a, bool live, const SparseArgs &rec, void *dst);
+void multi_pack_tti(int ndim, const TtiArgs &a, bool live, const SparseArgs &rec, void *dst1, void *dst2);
+hipError_t launch_iso_multi(int ndim, int R, const Geom &g, const void *recs, int n, int64_t rec_lanes,
+                            hipStream_t s);
+hipError_t launch_tti_multi(int ndim, int R, const Geom &g, const void *recs1, const void *recs2, int n,
+                            int64_t rec_lanes, hipStream_t s);
+hipError_t launch_interp_multi(const SparseArgs *recs, int n, int64_t max_lanes, hipStream_t s);
+
 // the lane-parallel receiver sampling reduces aligned groups of 4 or 8 lanes
 inline bool interp_lanes_ok(const SparseArgs &a) { return a.r == 2 && (a.ncorner == 4 || a.ncorner == 8); }
 

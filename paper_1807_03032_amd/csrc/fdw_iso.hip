@@ -13,11 +13,7 @@ namespace fdw {
 // ---------------------------------------------------------------------------
 
 template <int NDIM, int R>
-__global__ void __launch_bounds__(256) iso_naive(IsoArgs a) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
-    const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
-    if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+__device__ __forceinline__ void iso_naive_point(const IsoArgs &a, int x, int y, int z) {
     const int64_t i = a.g.off0 + (int64_t)z * a.g.sz + (int64_t)y * a.g.sy + x;
     const float *u = a.u_cur;
     const float uc = u[i];
@@ -28,6 +24,25 @@ __global__ void __launch_bounds__(256) iso_naive(IsoArgs a) {
     if (a.src.n) un = fused_inject(a.src, NDIM, x, y, z, rm, un, a.adjoint ? 1.0f / (1.0f + d) : 1.0f);
     a.u_next[i] = un;
     if (a.save) a.save[i] = un;
+}
+
+template <int NDIM, int R>
+__global__ void __launch_bounds__(256) iso_naive(IsoArgs a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
+    const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+    iso_naive_point<NDIM, R>(a, x, y, z);
+}
+
+// 2D shots of one geometry in one launch: blockIdx.z selects the shot.
+template <int R>
+__global__ void __launch_bounds__(256) iso2d_naive_multi(const NaiveShot<IsoArgs> *__restrict__ shots) {
+    const NaiveShot<IsoArgs> &S = shots[blockIdx.z];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int z = blockIdx.y * blockDim.y + threadIdx.y;
+    if (!S.live || x >= S.a.g.nx || z >= S.a.g.nz) return;
+    iso_naive_point<2, R>(S.a, x, 0, z);
 }
 
 // ---- isotropic step: stencil field u(t); pointwise u(t-1), m ----------------
@@ -225,23 +240,12 @@ static IsoShape iso_stream_shape(const Geom &g) {
     return sh;
 }
 
+static IsoOp make_iso_op(const IsoArgs &a);
+static StreamFields<1, 2> iso_fields(const IsoArgs &a);
+
 template <int R, int NY, int PF, int BY>
 static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t s, const LaunchEvents &ev) {
-    IsoOp op;
-    op.c = a.c;
-    op.eta = DampTables{a.eta_x, a.eta_y, a.eta_z};
-    op.dt2 = a.dt2;
-    op.src = a.src;
-    op.u_next = a.u_next;
-    op.save = a.save;
-    op.adjoint = a.adjoint;
-    StreamFields<1, 2> F;
-    F.q[0] = a.u_cur;
-    F.p[0] = a.u_prev;
-    F.p[1] = a.m;
-    F.pout[0] = 0.0f;
-    F.pout[1] = 1.0f;
-    return launch_stream3d<R, NY, PF, BY>(op, F, a.g, zc, s, ev.start, ev.stop, a.rec);
+    return launch_stream3d<R, NY, PF, BY>(make_iso_op(a), iso_fields(a), a.g, zc, s, ev.start, ev.stop, a.rec);
 }
 
 template <int R, int NY, int PF>
@@ -280,6 +284,74 @@ hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream
     FDW_DISPATCH_R(R, ISO_N2)
 #undef ISO_N3
 #undef ISO_N2
+}
+
+// ---------------------------------------------------------------------------
+// Fused multi-shot steps (same geometry and space order)
+// ---------------------------------------------------------------------------
+static IsoOp make_iso_op(const IsoArgs &a) {
+    IsoOp op;
+    op.c = a.c;
+    op.eta = DampTables{a.eta_x, a.eta_y, a.eta_z};
+    op.dt2 = a.dt2;
+    op.src = a.src;
+    op.u_next = a.u_next;
+    op.save = a.save;
+    op.adjoint = a.adjoint;
+    return op;
+}
+
+static StreamFields<1, 2> iso_fields(const IsoArgs &a) {
+    StreamFields<1, 2> F;
+    F.q[0] = a.u_cur;
+    F.p[0] = a.u_prev;
+    F.p[1] = a.m;
+    F.pout[0] = 0.0f;
+    F.pout[1] = 1.0f;
+    return F;
+}
+
+using IsoShot3 = StreamShot<IsoOp, 1, 2>;
+
+size_t iso_multi_record_bytes(int ndim) { return ndim == 3 ? sizeof(IsoShot3) : sizeof(NaiveShot<IsoArgs>); }
+
+void multi_pack_iso(int ndim, const IsoArgs &a, bool live, const SparseArgs &rec, void *dst) {
+    if (ndim == 3) {
+        IsoShot3 r;
+        std::memset(&r, 0, sizeof(r));
+        r.op = make_iso_op(a);
+        r.F = iso_fields(a);
+        r.rec = rec;
+        r.live = live ? 1 : 0;
+        std::memcpy(dst, &r, sizeof(r));
+    } else {
+        NaiveShot<IsoArgs> r;
+        std::memset(&r, 0, sizeof(r));
+        r.a = a;
+        r.a.rec = nullptr;  // host pointer: never read on the device
+        r.live = live ? 1 : 0;
+        std::memcpy(dst, &r, sizeof(r));
+    }
+}
+
+template <int R>
+static hipError_t launch_iso_multi_r(int ndim, const Geom &g, const void *recs, int n, int64_t rec_lanes,
+                                     hipStream_t s) {
+    if (ndim == 3) {
+        const IsoShape sh{2, 32, 2, 4};
+        return launch_stream3d_multi<R, 2, 2, 4>(static_cast<const IsoShot3 *>(recs), n, rec_lanes, g, sh.zc, s);
+    }
+    dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.nz + 3) / 4, n);
+    hipLaunchKernelGGL((iso2d_naive_multi<R>), grd, blk, 0, s, static_cast<const NaiveShot<IsoArgs> *>(recs));
+    return hipGetLastError();
+}
+
+hipError_t launch_iso_multi(int ndim, int R, const Geom &g, const void *recs, int n, int64_t rec_lanes,
+                            hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+#define ISO_M(r) launch_iso_multi_r<r>(ndim, g, recs, n, rec_lanes, s)
+    FDW_DISPATCH_R(R, ISO_M)
+#undef ISO_M
 }
 
 template <int R, bool HALO>

@@ -30,6 +30,12 @@ __global__ void __launch_bounds__(256) interp_point_kernel(SparseArgs a) {
     a.rec_row[p] = v;
 }
 
+// Receiver rows of several shots in one launch: blockIdx.y selects the shot.
+__global__ void __launch_bounds__(256) interp_multi_kernel(const SparseArgs *__restrict__ recs) {
+    const SparseArgs &a = recs[blockIdx.y];
+    interp_lane(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 __global__ void __launch_bounds__(256) inject_kernel(SparseArgs a) {
     const int lane = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = lane / a.ncorner;
@@ -98,6 +104,13 @@ hipError_t launch_interp(const SparseArgs &a, hipStream_t s) {
     }
     const int64_t lanes = (int64_t)a.npoint * a.ncorner;
     hipLaunchKernelGGL(interp_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp_multi(const SparseArgs *recs, int n, int64_t max_lanes, hipStream_t s) {
+    if (n <= 0 || max_lanes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(interp_multi_kernel, dim3((unsigned)((max_lanes + 255) / 256), (unsigned)n), dim3(256), 0, s,
+                       recs);
     return hipGetLastError();
 }
 

@@ -45,11 +45,7 @@ __device__ __forceinline__ float rot_grad(const float *f, int64_t i, const Geom 
 
 // TTI stage 1: gp = n . grad p, gr = n . grad r on every domain point.
 template <int NDIM, int R>
-__global__ void __launch_bounds__(256) tti_naive_stage1(TtiArgs a) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
-    const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
-    if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+__device__ __forceinline__ void tti_stage1_point(const TtiArgs &a, int x, int y, int z) {
     const int64_t i = a.g.off0 + (int64_t)z * a.g.sz + (int64_t)y * a.g.sy + x;
     float nx, ny, nz;
     tti_normal<NDIM>(a, i, nx, ny, nz);
@@ -57,13 +53,18 @@ __global__ void __launch_bounds__(256) tti_naive_stage1(TtiArgs a) {
     a.gr[i] = rot_grad<NDIM, R>(a.r_cur, i, a.g, a.c, nx, ny, nz);
 }
 
-// TTI stage 2: H p = n . grad gp, H r = n . grad gr, L p, coupled update.
 template <int NDIM, int R>
-__global__ void __launch_bounds__(256) tti_naive_stage2(TtiArgs a) {
+__global__ void __launch_bounds__(256) tti_naive_stage1(TtiArgs a) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
     const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
     if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+    tti_stage1_point<NDIM, R>(a, x, y, z);
+}
+
+// TTI stage 2: H p = n . grad gp, H r = n . grad gr, L p, coupled update.
+template <int NDIM, int R>
+__device__ __forceinline__ void tti_stage2_point(const TtiArgs &a, int x, int y, int z) {
     const int64_t i = a.g.off0 + (int64_t)z * a.g.sz + (int64_t)y * a.g.sy + x;
     float nx, ny, nz;
     tti_normal<NDIM>(a, i, nx, ny, nz);
@@ -85,6 +86,28 @@ __global__ void __launch_bounds__(256) tti_naive_stage2(TtiArgs a) {
     }
     a.p_next[i] = pn;
     a.r_next[i] = rn;
+}
+
+template <int NDIM, int R>
+__global__ void __launch_bounds__(256) tti_naive_stage2(TtiArgs a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
+    const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+    tti_stage2_point<NDIM, R>(a, x, y, z);
+}
+
+// 2D shots of one geometry in one launch: blockIdx.z selects the shot.
+template <int R, int STAGE>
+__global__ void __launch_bounds__(256) tti2d_naive_multi(const NaiveShot<TtiArgs> *__restrict__ shots) {
+    const NaiveShot<TtiArgs> &S = shots[blockIdx.z];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int z = blockIdx.y * blockDim.y + threadIdx.y;
+    if (!S.live || x >= S.a.g.nx || z >= S.a.g.nz) return;
+    if (STAGE == 1)
+        tti_stage1_point<2, R>(S.a, x, 0, z);
+    else
+        tti_stage2_point<2, R>(S.a, x, 0, z);
 }
 
 // n = (sin th cos ph, sin th sin ph, cos th) with the hardware sin/cos
@@ -237,29 +260,24 @@ static hipError_t launch_tti_stage_shape(int ny, int by, const Op &op, const Str
     }
 }
 
-template <int R>
-static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {
-    const TtiShape sh = tti_stream_shape(a.g);
-    TtiS1Op o1;
+static void tti_stage1_parts(const TtiArgs &a, TtiS1Op &o1, StreamFields<2, 2> &F1) {
     o1.c = a.c;
     o1.gp = a.gp;
     o1.gr = a.gr;
-    StreamFields<2, 2> F1;
     F1.q[0] = a.p_cur;
     F1.q[1] = a.r_cur;
     F1.p[0] = a.theta;
     F1.p[1] = a.phi;
     F1.pout[0] = F1.pout[1] = 0.0f;
-    hipError_t e = launch_tti_stage_shape<R>(sh.ny1, sh.by1, o1, F1, a.g, sh.zc, s, ev.start, nullptr, a.rec);
-    if (e != hipSuccess) return e;
-    TtiS2Op o2;
+}
+
+static void tti_stage2_parts(const TtiArgs &a, TtiS2Op &o2, StreamFields<3, 8> &F2) {
     o2.c = a.c;
     o2.eta = DampTables{a.eta_x, a.eta_y, a.eta_z};
     o2.dt2 = a.dt2;
     o2.src = a.src;
     o2.p_next = a.p_next;
     o2.r_next = a.r_next;
-    StreamFields<3, 8> F2;
     F2.q[0] = a.gp;
     F2.q[1] = a.gr;
     F2.q[2] = a.p_cur;
@@ -269,7 +287,80 @@ static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s, const Lau
         F2.pout[i] = 0.0f;
     }
     F2.pout[3] = 1.0f;  // m
+}
+
+template <int R>
+static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {
+    const TtiShape sh = tti_stream_shape(a.g);
+    TtiS1Op o1;
+    StreamFields<2, 2> F1;
+    tti_stage1_parts(a, o1, F1);
+    hipError_t e = launch_tti_stage_shape<R>(sh.ny1, sh.by1, o1, F1, a.g, sh.zc, s, ev.start, nullptr, a.rec);
+    if (e != hipSuccess) return e;
+    TtiS2Op o2;
+    StreamFields<3, 8> F2;
+    tti_stage2_parts(a, o2, F2);
     return launch_tti_stage_shape<R>(sh.ny2, sh.by2, o2, F2, a.g, sh.zc, s, nullptr, ev.stop);
+}
+
+// ---------------------------------------------------------------------------
+// Fused multi-shot steps (same geometry and space order)
+// ---------------------------------------------------------------------------
+using TtiShot1 = StreamShot<TtiS1Op, 2, 2>;
+using TtiShot2 = StreamShot<TtiS2Op, 3, 8>;
+
+size_t tti_multi_record_bytes(int ndim, int stage) {
+    if (ndim != 3) return sizeof(NaiveShot<TtiArgs>);
+    return stage == 1 ? sizeof(TtiShot1) : sizeof(TtiShot2);
+}
+
+void multi_pack_tti(int ndim, const TtiArgs &a, bool live, const SparseArgs &rec, void *dst1, void *dst2) {
+    if (ndim == 3) {
+        TtiShot1 r1;
+        TtiShot2 r2;
+        std::memset(&r1, 0, sizeof(r1));
+        std::memset(&r2, 0, sizeof(r2));
+        tti_stage1_parts(a, r1.op, r1.F);
+        tti_stage2_parts(a, r2.op, r2.F);
+        r1.rec = rec;  // sampled by stage 1, which only reads p(t)
+        r1.live = r2.live = live ? 1 : 0;
+        std::memcpy(dst1, &r1, sizeof(r1));
+        std::memcpy(dst2, &r2, sizeof(r2));
+    } else {
+        NaiveShot<TtiArgs> r;
+        std::memset(&r, 0, sizeof(r));
+        r.a = a;
+        r.a.rec = nullptr;  // host pointer: never read on the device
+        r.live = live ? 1 : 0;
+        std::memcpy(dst1, &r, sizeof(r));
+    }
+}
+
+template <int R>
+static hipError_t launch_tti_multi_r(int ndim, const Geom &g, const void *recs1, const void *recs2, int n,
+                                     int64_t rec_lanes, hipStream_t s) {
+    if (ndim == 3) {
+        constexpr int NY1 = 2, BY1 = 8, NY2 = 1, BY2 = 8;
+        hipError_t e = launch_stream3d_multi<R, NY1, 1, BY1>(static_cast<const TtiShot1 *>(recs1), n, rec_lanes, g,
+                                                             64, s);
+        if (e != hipSuccess) return e;
+        return launch_stream3d_multi<R, NY2, 1, BY2>(static_cast<const TtiShot2 *>(recs2), n, 0, g, 64, s);
+    }
+    const auto *sh = static_cast<const NaiveShot<TtiArgs> *>(recs1);
+    dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.nz + 3) / 4, n);
+    hipLaunchKernelGGL((tti2d_naive_multi<R, 1>), grd, blk, 0, s, sh);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((tti2d_naive_multi<R, 2>), grd, blk, 0, s, sh);
+    return hipGetLastError();
+}
+
+hipError_t launch_tti_multi(int ndim, int R, const Geom &g, const void *recs1, const void *recs2, int n,
+                            int64_t rec_lanes, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+#define TTI_M(r) launch_tti_multi_r<r>(ndim, g, recs1, recs2, n, rec_lanes, s)
+    FDW_DISPATCH_R(R, TTI_M)
+#undef TTI_M
 }
 
 hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {

@@ -41,8 +41,11 @@ EXPORTS = (
     "fdw_operator_create", "fdw_operator_apply", "fdw_sync", "fdw_operator_destroy",
     "fdw_operator_set_timing", "fdw_operator_kernel_time", "fdw_operator_describe", "fdw_stable_dt",
     "fdw_last_error", "fdw_version", "fdw_operator_set_save", "fdw_gradient_accumulate",
-    "fdw_sparse_bind_precomputed",
+    "fdw_sparse_bind_precomputed", "fdw_batch_create", "fdw_batch_apply", "fdw_batch_stats", "fdw_batch_destroy",
+    "fdw_server_create", "fdw_server_footprint", "fdw_server_submit", "fdw_server_progress", "fdw_server_info",
+    "fdw_server_fetch", "fdw_server_release", "fdw_server_stats", "fdw_server_destroy",
 )
+FDW_SHOT_QUEUED, FDW_SHOT_RUNNING, FDW_SHOT_DONE = 0, 1, 2
 
 
 class FdwError(RuntimeError):
@@ -65,6 +68,29 @@ class fdw_op_desc(ctypes.Structure):
                 ("m", ctypes.c_void_p), ("eps", ctypes.c_void_p), ("delta", ctypes.c_void_p),
                 ("theta", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("src", ctypes.c_void_p),
                 ("rec", ctypes.c_void_p), ("mode", ctypes.c_int)]
+
+
+class fdw_shot_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("ndim", ctypes.c_int), ("shape", ctypes.c_int64 * 3),
+                ("extent", ctypes.c_double * 3), ("origin", ctypes.c_double * 3), ("space_order", ctypes.c_int),
+                ("nt", ctypes.c_int), ("dt", ctypes.c_double), ("nbl", ctypes.c_int), ("damp_rc", ctypes.c_double),
+                ("vmax", ctypes.c_double), ("eps_max", ctypes.c_double), ("m", ctypes.c_void_p),
+                ("eps", ctypes.c_void_p), ("delta", ctypes.c_void_p), ("theta", ctypes.c_void_p),
+                ("phi", ctypes.c_void_p), ("nsrc", ctypes.c_int), ("src_coords", ctypes.c_void_p),
+                ("src", ctypes.c_void_p), ("nrec", ctypes.c_int), ("rec_coords", ctypes.c_void_p),
+                ("keep_field", ctypes.c_int)]
+
+
+class fdw_shot_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("steps_done", ctypes.c_int), ("footprint", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class fdw_server_stats_t(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_int64), ("used", ctypes.c_int64), ("pool_bytes", ctypes.c_int64),
+                ("chunks", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("buckets", ctypes.c_int64), ("graph_builds", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
+                ("now", ctypes.c_double)]
 
 
 _lib = None
@@ -102,6 +128,19 @@ def load(path: str = LIB_PATH):
         "fdw_stable_dt": (dbl, [i32, i32, i32, dbl, dbl, dbl]),
         "fdw_operator_set_save": (i32, [vp, vp, i64, i32, i32]),
         "fdw_gradient_accumulate": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+        "fdw_batch_create": (i32, [pvp]),
+        "fdw_batch_apply": (i32, [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]),
+        "fdw_batch_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "fdw_batch_destroy": (i32, [vp]),
+        "fdw_server_create": (i32, [i64, i32, i32, pvp]),
+        "fdw_server_footprint": (i32, [ctypes.POINTER(fdw_shot_desc), ctypes.POINTER(i64)]),
+        "fdw_server_submit": (i32, [vp, ctypes.POINTER(fdw_shot_desc), ctypes.POINTER(i64)]),
+        "fdw_server_progress": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "fdw_server_info": (i32, [vp, i64, ctypes.POINTER(fdw_shot_info)]),
+        "fdw_server_fetch": (i32, [vp, i64, vp, vp]),
+        "fdw_server_release": (i32, [vp, i64]),
+        "fdw_server_stats": (i32, [vp, ctypes.POINTER(fdw_server_stats_t)]),
+        "fdw_server_destroy": (i32, [vp]),
         "fdw_last_error": (ctypes.c_char_p, []),
         "fdw_version": (ctypes.c_char_p, []),
     }
@@ -393,6 +432,139 @@ class Shot:
             for h in list(self.fn.values()):
                 fdw_function_destroy(h)
             fdw_grid_destroy(self.grid)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- batches
+def fdw_batch_create() -> int:
+    out = ctypes.c_void_p()
+    _chk(load().fdw_batch_create(ctypes.byref(out)))
+    return out.value
+
+
+def fdw_batch_apply(b, ops, time_m, time_M, stream=None):
+    n = len(ops)
+    arr = (ctypes.c_void_p * n)(*ops)
+    tm = (ctypes.c_int * n)(*[int(t) for t in time_m])
+    tM = (ctypes.c_int * n)(*[int(t) for t in time_M])
+    _chk(load().fdw_batch_apply(b, arr, n, tm, tM, stream))
+
+
+def fdw_batch_stats(b):
+    gb, gl = ctypes.c_int64(), ctypes.c_int64()
+    _chk(load().fdw_batch_stats(b, ctypes.byref(gb), ctypes.byref(gl)))
+    return gb.value, gl.value
+
+
+def fdw_batch_destroy(b):
+    _chk(load().fdw_batch_destroy(b))
+
+
+# ----------------------------------------------------------------- server
+def shot_desc(prob, keep_field: bool = False):
+    """fdw_shot_desc of a workloads.Problem plus the numpy arrays it borrows
+    (keep them alive until the shot is admitted)."""
+    kind = FDW_TTI if prob.kind == "tti" else FDW_ISO
+    d = fdw_shot_desc()
+    nd = prob.ndim
+    d.kind, d.ndim = kind, nd
+    for a in range(3):
+        d.shape[a] = int(prob.shape[a]) if a < nd else 1
+        d.extent[a] = float(prob.extent[a]) if a < nd else 0.0
+        d.origin[a] = float(prob.origin[a]) if a < nd else 0.0
+    d.space_order, d.nt, d.dt, d.nbl = prob.so, prob.nt, prob.dt, prob.nbl
+    d.damp_rc, d.vmax, d.eps_max = prob.rc, prob.vmax, prob.eps_max
+    keep = []
+
+    def f32p(a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        keep.append(a)
+        return a.ctypes.data
+
+    def f64p(a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data
+
+    d.m = f32p(prob.fields["m"])
+    if kind == FDW_TTI:
+        d.eps, d.delta, d.theta = (f32p(prob.fields[k]) for k in ("eps", "delta", "theta"))
+        d.phi = f32p(prob.fields["phi"]) if nd == 3 else None
+    d.nsrc = prob.src_coords.shape[0]
+    if d.nsrc:
+        d.src_coords = f64p(prob.src_coords)
+        d.src = f32p(prob.src)
+    d.nrec = prob.rec_coords.shape[0]
+    if d.nrec:
+        d.rec_coords = f64p(prob.rec_coords)
+    d.keep_field = 1 if keep_field else 0
+    return d, keep
+
+
+class Server:
+    """Thin wrapper of the fdw_server C ABI."""
+
+    def __init__(self, budget_bytes: int = 0, chunk_target_us: int = 0, nstreams: int = 4):
+        out = ctypes.c_void_p()
+        _chk(load().fdw_server_create(int(budget_bytes), int(chunk_target_us), int(nstreams), ctypes.byref(out)))
+        self.h = out.value
+        self.borrowed = {}
+        self.meta = {}
+
+    @staticmethod
+    def footprint(prob) -> int:
+        d, _ = shot_desc(prob)
+        out = ctypes.c_int64()
+        _chk(load().fdw_server_footprint(ctypes.byref(d), ctypes.byref(out)))
+        return out.value
+
+    def submit(self, prob, keep_field: bool = False) -> int:
+        d, keep = shot_desc(prob, keep_field)
+        t = ctypes.c_int64()
+        _chk(load().fdw_server_submit(self.h, ctypes.byref(d), ctypes.byref(t)))
+        self.borrowed[t.value] = keep
+        self.meta[t.value] = (prob.nt, prob.rec_coords.shape[0], prob.array_shape)
+        return t.value
+
+    def progress(self):
+        q, r = ctypes.c_int(), ctypes.c_int()
+        _chk(load().fdw_server_progress(self.h, ctypes.byref(q), ctypes.byref(r)))
+        # host arrays of admitted shots are no longer borrowed
+        for t in [t for t in self.borrowed if self.info(t).state != FDW_SHOT_QUEUED]:
+            del self.borrowed[t]
+        return q.value, r.value
+
+    def info(self, ticket: int) -> fdw_shot_info:
+        out = fdw_shot_info()
+        _chk(load().fdw_server_info(self.h, int(ticket), ctypes.byref(out)))
+        return out
+
+    def fetch(self, ticket: int, field: bool = False):
+        nt, nrec, ash = self.meta[ticket]
+        rec = np.zeros((nt, nrec), dtype=np.float32)
+        fld = np.zeros(ash, dtype=np.float32) if field else None
+        _chk(load().fdw_server_fetch(self.h, int(ticket), rec.ctypes.data if nrec else None,
+                                     fld.ctypes.data if field else None))
+        return rec, fld
+
+    def release(self, ticket: int):
+        _chk(load().fdw_server_release(self.h, int(ticket)))
+        self.meta.pop(ticket, None)
+
+    def stats(self) -> dict:
+        out = fdw_server_stats_t()
+        _chk(load().fdw_server_stats(self.h, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in out._fields_}
+
+    def close(self):
+        if self.h:
+            _chk(load().fdw_server_destroy(self.h))
+            self.h = None
 
     def __del__(self):
         try:

@@ -288,3 +288,63 @@ def lagrange_support(shape, spacing, origin, coords, r: int):
                         den *= j - k
                 cf[p, a, j] = num / den
     return gp, cf
+
+
+# ---------------------------------------------------------------------------
+# Served shot stream: Poisson arrivals of forward-modelling requests with
+# grids from 2D 201^2 to 3D 400^3, space order in {4, 8, 12, 16}, 500-2000
+# steps, isotropic or TTI, seeded smooth random models, a random source near
+# the surface and a receiver line.
+# ---------------------------------------------------------------------------
+SERVE_SIZES = ((2, 201), (2, 401), (2, 801), (3, 100), (3, 200), (3, 300), (3, 400))
+
+
+def serve_problem(kind: str, ndim: int, n: int, so: int, nt: int, seed: int, model_cache=None, h: float = 10.0,
+                  nbl: int = 20, vrange=(1500.0, 4500.0)) -> Problem:
+    """One request of the served stream: n^ndim grid, smooth random model
+    (seeded by kind, ndim and n, shared through `model_cache`), 10 Hz Ricker
+    source at a seeded random (x, y) position two points below the top damping
+    layer, receivers every grid point along x on a line at that depth."""
+    shape = (n,) * ndim
+    extent = tuple(h * (k - 1) for k in shape)
+    key = (kind, ndim, n)
+    if model_cache is not None and key in model_cache:
+        fields, eps_max = model_cache[key]
+    else:
+        mseed = 1000 + 10 * ndim + n + (5000 if kind == "tti" else 0)
+        v = smooth_field(shape, mseed, vrange[0], vrange[1], sigma_pts=10.0)
+        fields, eps_max = _physical_models(kind, shape, v, mseed)
+        if model_cache is not None:
+            model_cache[key] = (fields, eps_max)
+    vmax = float(vrange[1])
+    v_eff = vmax * math.sqrt(1.0 + 2.0 * 0.3) if kind == "tti" else vmax
+    dt = cfl_dt(h, v_eff, ndim)
+    rng = np.random.default_rng(seed)
+    depth = (nbl + 2) * h
+    pos = rng.uniform(0.25, 0.75, size=ndim - 1) * np.asarray(extent[:ndim - 1])
+    src_coords = np.array([[*pos, depth]])
+    src = ricker(10.0, 0.1, dt, nt)[:, None]
+    xs = np.arange(n) * h
+    if ndim == 3:
+        rec_coords = np.stack([xs, np.full(n, pos[1]), np.full(n, depth)], axis=1)
+    else:
+        rec_coords = np.stack([xs, np.full(n, depth)], axis=1)
+    return Problem(f"serve_{kind}_{ndim}d_{n}_so{so}_nt{nt}_s{seed}", kind, shape, extent, (0.0,) * ndim, so, nbl, nt,
+                   dt, vmax, eps_max, fields, src_coords, f32(src), rec_coords)
+
+
+def serve_stream(count: int = 24, seed: int = 7, rate_hz: float = 3.0, sizes=SERVE_SIZES, sos=(4, 8, 12, 16),
+                 nt_range=(500, 2000), kinds=("iso", "tti"), model_cache=None):
+    """[(arrival time in s, Problem)] with exponential inter-arrival times of
+    mean 1/rate_hz (all seeded)."""
+    rng = np.random.default_rng(seed)
+    cache = {} if model_cache is None else model_cache
+    out, t = [], 0.0
+    for i in range(count):
+        t += float(rng.exponential(1.0 / rate_hz)) if rate_hz > 0 else 0.0
+        ndim, n = sizes[int(rng.integers(len(sizes)))]
+        so = int(sos[int(rng.integers(len(sos)))])
+        nt = int(rng.integers(nt_range[0], nt_range[1] + 1))
+        kind = kinds[int(rng.integers(len(kinds)))]
+        out.append((t, serve_problem(kind, ndim, n, so, nt, seed * 1000 + i, cache)))
+    return out

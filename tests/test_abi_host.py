@@ -201,3 +201,32 @@ def test_precomputed_sparse_validation():
     s = fdw.fdw_sparse_bind_precomputed(g, "s", np.array([[8, 6, 5]]), np.full((1, 3, 4), 0.25), 10, fake)
     fdw.fdw_sparse_destroy(s)
     fdw.fdw_grid_destroy(g)
+
+
+@pytest.mark.parametrize("kind,ndim,n,so", [("iso", 3, 64, 8), ("tti", 3, 48, 12), ("iso", 2, 201, 4), ("tti", 2, 97, 16)])
+def test_server_footprint(kind, ndim, n, so):
+    """Device bytes of a served shot: two slots per wavefield, the model
+    parameters, TTI stage buffers, source / receiver samples and small tables."""
+    from paper_1807_03032_amd import workloads as W
+    prob = W.serve_problem(kind, ndim, n, so, 30, seed=1, nbl=10)
+    got = fdw.Server.footprint(prob)
+    g = fdw.fdw_grid_create(prob.shape, prob.extent)
+    E = fdw.fdw_field_layout(g, so).elems_per_slot
+    fdw.fdw_grid_destroy(g)
+    slots = {"iso": 2 + 1, "tti": 4 + (5 if ndim == 3 else 4) + 2}[kind]
+    nrec = prob.rec_coords.shape[0]
+    floats = slots * E + 30 * (1 + nrec) + ndim * n + (1 + nrec) * (2 + 2 ** ndim + 3)
+    assert got == 4 * floats + 64 * 256
+
+
+def test_server_footprint_validation():
+    from paper_1807_03032_amd import workloads as W
+    prob = W.serve_problem("iso", 2, 50, 8, 10, seed=2, nbl=5)
+    d, keep = fdw.shot_desc(prob)
+    d.kind = 5
+    import ctypes
+    out = ctypes.c_int64()
+    assert fdw.load().fdw_server_footprint(ctypes.byref(d), ctypes.byref(out)) == fdw.FDW_ERR_ARG
+    d.kind, d.space_order = fdw.FDW_ISO, 7
+    assert fdw.load().fdw_server_footprint(ctypes.byref(d), ctypes.byref(out)) == fdw.FDW_ERR_ARG
+    assert "space order" in fdw.fdw_last_error() or "space_order" in fdw.fdw_last_error()

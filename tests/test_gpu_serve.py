@@ -1,0 +1,159 @@
+"""GPU tests of the fused multi-shot steps (fdw_batch_apply) and of the shot
+server (continuous batching): every shot's result is the same alone and in
+a mix, bit for bit, the server keeps within its device-memory budget, and
+served results match the FP64 oracle within the parity bar (relative L2 <=
+1e-4)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_03032_amd import workloads as W
+
+from test_gpu_parity import TOL, rel_l2, say, torch_dev  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def run_alone(prob, dev):
+    """Plain per-shot solve through fdw_operator_apply (two-slot storage)."""
+    from paper_1807_03032_amd import fdw
+    shot = fdw.Shot(prob, dev, nslots=2)
+    try:
+        shot.apply(0, prob.nt - 1)
+        f = shot.fields(prob.nt - 1)
+        tr = shot.traces()
+    finally:
+        shot.close()
+    return tr, f
+
+
+@pytest.mark.parametrize("kind,ndim,n,so", [("iso", 3, 40, 8), ("tti", 3, 36, 12), ("iso", 2, 203, 4),
+                                            ("tti", 2, 201, 16), ("iso", 3, 33, 16)])
+def test_batch_equals_single(torch_dev, kind, ndim, n, so):
+    import torch
+
+    from paper_1807_03032_amd import fdw
+    probs = [W.serve_problem(kind, ndim, n, so, nt, seed=s, nbl=8) for s, nt in ((1, 37), (2, 52), (3, 45))]
+    say("batch", kind, ndim, n, so)
+    ref = [run_alone(p, torch_dev) for p in probs]
+    shots = [fdw.Shot(p, torch_dev, nslots=2) for p in probs]
+    batches = [fdw.fdw_batch_create(), fdw.fdw_batch_create()]
+    side = torch.cuda.Stream(torch_dev)
+    try:
+        t = [0] * len(probs)
+        calls = 0
+        while any(t[i] < p.nt for i, p in enumerate(probs)):
+            # shots leave the batch when done: the shot count (and graph) changes
+            idx = [i for i, p in enumerate(probs) if t[i] < p.nt]
+            tm = [t[i] for i in idx]
+            tM = [min(t[i] + 16, probs[i].nt) - 1 for i in idx]
+            fdw.fdw_batch_apply(batches[calls % 2], [shots[i].op for i in idx], tm, tM, side.cuda_stream)
+            for i, hi in zip(idx, tM):
+                t[i] = hi + 1
+            calls += 1
+        side.synchronize()
+        builds = sum(fdw.fdw_batch_stats(b)[0] for b in batches)
+        launches = sum(fdw.fdw_batch_stats(b)[1] for b in batches)
+        assert launches == calls and 1 <= builds < calls
+        for i, p in enumerate(probs):
+            f = shots[i].fields(p.nt - 1)
+            tr = shots[i].traces()
+            for nm in f:
+                np.testing.assert_array_equal(f[nm][1], ref[i][1][nm][1])
+                np.testing.assert_array_equal(f[nm][0], ref[i][1][nm][0])
+            np.testing.assert_array_equal(tr, ref[i][0])
+    finally:
+        for b in batches:
+            fdw.fdw_batch_destroy(b)
+        for s in shots:
+            s.close()
+
+
+def serve_all(reqs, budget=0, chunk_us=40, stagger=0, keep_field=True, watch=None):
+    """Run requests through one server; `stagger` progress rounds between
+    submissions.  Returns ({index: (traces, field)}, server stats)."""
+    from paper_1807_03032_amd import fdw
+    sv = fdw.Server(budget_bytes=budget, chunk_target_us=chunk_us, nstreams=3)
+    try:
+        tickets = []
+        pending = list(range(len(reqs)))
+        out = {}
+        deadline = time.time() + 120
+        while len(out) < len(reqs):
+            assert time.time() < deadline, "server did not finish"
+            if pending:
+                i = pending.pop(0)
+                tickets.append((i, sv.submit(reqs[i], keep_field=keep_field)))
+            for _ in range(stagger if pending else 1):
+                sv.progress()
+                if watch:
+                    watch(sv.stats())
+            for i, tk in tickets:
+                if i not in out and sv.info(tk).state == fdw.FDW_SHOT_DONE:
+                    out[i] = sv.fetch(tk, field=keep_field)
+                    sv.release(tk)
+            if not pending:
+                time.sleep(1e-4)
+        return out, sv.stats()
+    finally:
+        sv.close()
+
+
+def mixed_requests():
+    return [W.serve_problem("iso", 2, 201, 8, 60, seed=11, nbl=10),
+            W.serve_problem("tti", 2, 201, 8, 80, seed=12, nbl=10),
+            W.serve_problem("iso", 3, 40, 8, 70, seed=13, nbl=8),
+            W.serve_problem("iso", 3, 40, 8, 50, seed=14, nbl=8),   # same bucket as the previous one
+            W.serve_problem("tti", 3, 36, 12, 40, seed=15, nbl=8),
+            W.serve_problem("iso", 3, 48, 16, 30, seed=16, nbl=8),
+            W.serve_problem("iso", 2, 201, 8, 45, seed=17, nbl=10)]  # joins the first bucket late
+
+
+def test_server_alone_and_in_the_mix(torch_dev):
+    reqs = mixed_requests()
+    say("server alone")
+    alone = {i: serve_all([r])[0][0] for i, r in enumerate(reqs)}
+    say("server mix")
+    mix, stats = serve_all(reqs, stagger=2)
+    say("stats", stats)
+    assert stats["completed"] == len(reqs) and stats["buckets"] == 5
+    assert stats["graph_launches"] > stats["graph_builds"]
+    for i in range(len(reqs)):
+        np.testing.assert_array_equal(mix[i][0], alone[i][0])
+        np.testing.assert_array_equal(mix[i][1], alone[i][1])
+    # a served result against the plain per-shot solve and the oracle
+    for i in (2, 6):
+        tr, f = run_alone(reqs[i], torch_dev)
+        if reqs[i].ndim == 3:  # same kernels in 3D: same bits
+            np.testing.assert_array_equal(mix[i][0], tr)
+        p = reqs[i]
+        g = oracle.Grid(p.shape, p.extent, p.origin, so=p.so, dt=p.dt, nbl=p.nbl, vmax=p.vmax, rc=p.rc)
+        _, uc, rec = oracle.iso_run(g, p.fields["m"], p.nt, src_coords=p.src_coords, src=p.src,
+                                    rec_coords=p.rec_coords)
+        e_f, e_r = rel_l2(mix[i][1], uc), rel_l2(mix[i][0], rec)
+        say("oracle", p.name, f"{e_f:.2e}", f"{e_r:.2e}")
+        assert e_f <= TOL and e_r <= TOL
+
+
+def test_server_keeps_within_budget(torch_dev):
+    from paper_1807_03032_amd import fdw
+    reqs = [W.serve_problem("iso", 3, 48, 8, 40, seed=20 + k, nbl=8) for k in range(4)]
+    reqs.append(W.serve_problem("iso", 2, 201, 4, 40, seed=30, nbl=10))
+    fps = [fdw.Server.footprint(r) for r in reqs]
+    budget = 2 * fps[0] + fps[-1]  # two 3D shots at a time, and the 2D one beside them
+    seen = []
+    out, stats = serve_all(reqs, budget=budget, keep_field=False, watch=lambda s: seen.append(s["used"]))
+    say("budget", budget, "peak used", max(seen))
+    assert max(seen) <= budget
+    assert max(seen) >= 2 * fps[0]
+    assert len(out) == len(reqs)
+    big = W.serve_problem("iso", 3, 64, 8, 10, seed=40, nbl=8)
+    sv = fdw.Server(budget_bytes=fps[0], nstreams=1)
+    try:
+        with pytest.raises(fdw.FdwError) as e:
+            sv.submit(big)
+        assert e.value.code == fdw.FDW_ERR_NOMEM
+    finally:
+        sv.close()
