@@ -42,6 +42,13 @@ def parse():
     ap.add_argument("--adjoint", action="store_true",
                     help="also time one gradient (forward with checkpoints + recomputation + adjoint + imaging) "
                          "on the 320^3 so=8 1500-step workload")
+    ap.add_argument("--serve", action="store_true",
+                    help="also run the served shot stream (Poisson arrivals, mixed sizes, kinds and orders): "
+                         "p50/p99 latency and aggregate GPts/s against sequential per-shot solves")
+    ap.add_argument("--serve-count", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=3.0, help="mean request arrivals per second")
+    ap.add_argument("--save-every", type=int, default=0,
+                    help="also time the isotropic workload while saving every k-th level (snapshots)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -81,6 +88,150 @@ def time_shot(prob, steps, warmup, device, nslots=3, timing_every=10):
     f = shot.fields(steps - 1) if steps <= prob.nt else None
     shot.close()
     return wall, kms, launches, desc, alg_bytes, tr, f
+
+
+def snapshot_leg(prob, every, device):
+    """The isotropic workload with every `every`-th level saved into a device
+    buffer (subsampled saving fused into the stencil kernel)."""
+    import torch
+
+    from paper_1807_03032_amd import fdw
+
+    shot = fdw.Shot(prob, device, nslots=2)
+    try:
+        nlev = prob.nt // every + 1
+        buf = torch.empty(nlev * shot.lay.elems_per_slot, dtype=torch.float32, device=device)
+        fdw.fdw_operator_set_save(shot.op, buf.data_ptr(), nlev, every, 0)
+        shot.apply(0, 19)
+        torch.cuda.synchronize(device)
+        t0 = time.perf_counter()
+        shot.apply(0, prob.nt - 1)
+        torch.cuda.synchronize(device)
+        wall = time.perf_counter() - t0
+    finally:
+        shot.close()
+    return {"every": every, "levels": nlev, "buffer_gib": round(nlev * shot.lay.elems_per_slot * 4 / 2 ** 30, 2),
+            "value": round(prob.npoints * prob.nt / wall / 1e9, 3), "unit": "GPts/s",
+            "ms_per_step": round(wall * 1e3 / prob.nt, 5)}
+
+
+def run_server(reqs, arrivals, chunk_us=20000, nstreams=4):
+    """Serve requests arriving at the given times (seconds from the start; all
+    zero = one burst).  Returns per-request latencies, the makespan and stats."""
+    from paper_1807_03032_amd import fdw
+
+    sv = fdw.Server(budget_bytes=0, chunk_target_us=chunk_us, nstreams=nstreams)
+    try:
+        t0 = sv.stats()["now"]
+        order = sorted(range(len(reqs)), key=lambda i: arrivals[i])
+        k, tickets, lat, done_at = 0, {}, {}, []
+        while len(lat) < len(reqs):
+            now = sv.stats()["now"] - t0
+            while k < len(order) and arrivals[order[k]] <= now:
+                i = order[k]
+                tickets[i] = sv.submit(reqs[i])
+                k += 1
+            q, r = sv.progress()
+            for i, tk in tickets.items():
+                if i in lat:
+                    continue
+                inf = sv.info(tk)
+                if inf.state == fdw.FDW_SHOT_DONE:
+                    lat[i] = inf.t_done - inf.t_submit
+                    done_at.append(inf.t_done - t0)
+                    sv.release(tk)
+            if q == 0 and r == 0 and k < len(order):
+                time.sleep(max(0.0, min(arrivals[order[k]] - now, 0.01)))
+            else:
+                time.sleep(2e-4)
+        st = sv.stats()
+        return lat, max(done_at), st
+    finally:
+        sv.close()
+
+
+def serve_leg(device, count, rate, seed=7):
+    """Served shot stream: Poisson arrivals (rate per second) of requests with
+    grids from 2D 201^2 to 3D 400^3, orders 4-16, 500-2000 steps, iso or TTI;
+    then the same requests as one burst, and as sequential per-shot solves."""
+    import numpy as np
+    import torch
+
+    from paper_1807_03032_amd import fdw
+    from paper_1807_03032_amd import workloads as W
+
+    t_gen = time.perf_counter()
+    stream = W.serve_stream(count=count, seed=seed, rate_hz=rate)
+    t_gen = time.perf_counter() - t_gen
+    reqs = [p for _, p in stream]
+    arrivals = [a for a, _ in stream]
+    work = sum(p.npoints * p.nt for p in reqs)
+    # warm-up: one small request of each kind through the server (kernel loading)
+    run_server([W.serve_problem(k, nd, n, 8, 20, seed=1) for k in ("iso", "tti") for nd, n in ((2, 201), (3, 48))],
+               [0.0] * 4)
+    lat, span, st = run_server(reqs, arrivals)
+    lat_b, span_b, st_b = run_server(reqs, [0.0] * len(reqs))
+    # sequential plain per-shot solves (set-up, all steps, traces), back to back
+    torch.cuda.synchronize(device)
+    t0 = time.perf_counter()
+    for p in reqs:
+        shot = fdw.Shot(p, device, nslots=2)
+        shot.apply(0, p.nt - 1)
+        shot.traces()
+        shot.close()
+    torch.cuda.synchronize(device)
+    seq = time.perf_counter() - t0
+    lv = np.array([lat[i] for i in range(len(reqs))])
+    mix = {}
+    for p in reqs:
+        key = f"{p.kind}{p.ndim}d"
+        mix[key] = mix.get(key, 0) + 1
+    return {
+        "workload": f"{count} requests, Poisson arrivals at {rate}/s, grids 2D 201^2..801^2 and 3D 100^3..400^3, "
+                    f"so in {{4,8,12,16}}, 500-2000 steps, iso/TTI (seed {seed})",
+        "mix": mix, "gpoint_steps": round(work / 1e9, 2),
+        "latency_p50_s": round(float(np.percentile(lv, 50)), 4),
+        "latency_p99_s": round(float(np.percentile(lv, 99)), 4),
+        "aggregate_gpts_poisson": round(work / span / 1e9, 2),
+        "aggregate_gpts_burst": round(work / span_b / 1e9, 2),
+        "sequential_gpts": round(work / seq / 1e9, 2),
+        "burst_vs_sequential": round(seq / span_b, 3),
+        "burst_latency_p50_s": round(float(np.percentile(list(lat_b.values()), 50)), 4),
+        "chunks": st["chunks"], "graph_builds": st["graph_builds"], "graph_launches": st["graph_launches"],
+        "host_admit_s": round(st["admit_seconds"], 3), "host_launch_s": round(st["launch_seconds"], 3),
+        "burst_host_admit_s": round(st_b["admit_seconds"], 3), "burst_makespan_s": round(span_b, 3),
+        "sequential_s": round(seq, 3),
+        "model_generation_s": round(t_gen, 1),
+    }
+
+
+def fused_burst_leg(device, count=32, n=401, so=8, nt=1000):
+    """Same-shape burst: `count` isotropic 2D n^2 shots (different sources)
+    served as one bucket (fused launches, replayed graphs) against sequential
+    per-shot solves."""
+    import torch
+
+    from paper_1807_03032_amd import fdw
+    from paper_1807_03032_amd import workloads as W
+
+    cache = {}
+    reqs = [W.serve_problem("iso", 2, n, so, nt, seed=100 + i, model_cache=cache) for i in range(count)]
+    run_server(reqs[:2], [0.0, 0.0])
+    work = sum(p.npoints * p.nt for p in reqs)
+    lat, span, st = run_server(reqs, [0.0] * count)
+    torch.cuda.synchronize(device)
+    t0 = time.perf_counter()
+    for p in reqs:
+        shot = fdw.Shot(p, device, nslots=2)
+        shot.apply(0, p.nt - 1)
+        shot.traces()
+        shot.close()
+    torch.cuda.synchronize(device)
+    seq = time.perf_counter() - t0
+    return {"workload": f"{count} isotropic 2D {n}^2 so={so} shots of {nt} steps, one burst",
+            "served_gpts": round(work / span / 1e9, 2), "sequential_gpts": round(work / seq / 1e9, 2),
+            "speedup": round(seq / span, 2), "chunks": st["chunks"], "graph_launches": st["graph_launches"],
+            "host_admit_s": round(st["admit_seconds"], 3), "makespan_s": round(span, 4), "sequential_s": round(seq, 4)}
 
 
 def parity_vs_stored(name, prob, steps, tr, f):
@@ -336,6 +487,11 @@ def main():
             line["tti"]["parity_rel_l2_sampled"] = p2
     if args.adjoint:
         line["adjoint"] = adjoint_leg(dev)
+    if args.save_every > 0:
+        line["snapshots"] = snapshot_leg(prob, args.save_every, dev)
+    if args.serve:
+        line["serve"] = serve_leg(dev, args.serve_count, args.serve_rate)
+        line["serve_fused_burst"] = fused_burst_leg(dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     if os.environ.get("FDW_BENCH_OPS_OUT"):

@@ -317,6 +317,8 @@ typedef struct {
     int64_t chunks, admitted, completed, buckets;
     int64_t graph_builds, graph_launches;
     double now;                /* the server's clock (seconds since creation)            */
+    double admit_seconds;      /* host time spent admitting (uploads, operator set-up)   */
+    double launch_seconds;     /* host time spent packing and enqueueing chunks          */
 } fdw_server_stats_t;
 
 typedef struct fdw_server fdw_server;

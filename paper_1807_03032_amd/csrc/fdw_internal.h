@@ -101,6 +101,9 @@ struct NaiveShot {
 // sample the receiver row `rec` inside the stencil launch; 2D steps sample it
 // with launch_interp_multi after the step.  live = 0: the shot's stencil is
 // skipped (its receiver row, if any, is still sampled).
+// logical (x fastest) device array -> domain of a padded slot of geometry g
+hipError_t launch_pad_copy(const Geom &g, const float *src, float *dst, hipStream_t s);
+
 // sets the thread-local message fdw_last_error returns; returns code
 int set_error(int code, const char *msg);
 

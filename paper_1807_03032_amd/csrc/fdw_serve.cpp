@@ -115,6 +115,7 @@ struct fdw_server {
     std::vector<Shot *> graveyard;       // retired shots whose library objects await destruction
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
     int64_t chunks = 0, admitted = 0, completed = 0;
+    double admit_s = 0, launch_s = 0;  // host time in admissions / chunk enqueueing
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -225,20 +226,25 @@ std::string bucket_key(const fdw_shot_desc &d) {
     return buf;
 }
 
-// logical host array (x fastest) -> padded device slot
-int upload_field(const fdw_layout &L, int ndim, const float *host, float *dev, hipStream_t s) {
-    const int64_t nx = L.shape[0];
-    const int64_t ny = ndim == 3 ? L.shape[1] : 1;
-    const int64_t nz = ndim == 3 ? L.shape[2] : L.shape[1];
-    const int64_t plane = L.pitch_x * L.pitch_y;
-    for (int64_t z = 0; z < nz; ++z) {
-        float *dst = dev + L.origin_offset + (ndim == 3 ? z * plane : z * L.pitch_x);
-        const float *src = host + z * ny * nx;
-        const int64_t rows = ndim == 3 ? ny : 1;
-        hipError_t e = hipMemcpy2DAsync(dst, (size_t)L.pitch_x * 4, src, (size_t)nx * 4, (size_t)nx * 4, (size_t)rows,
-                                        hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return sfail_hip(e, "server: model upload");
-    }
+fdw::Geom layout_geom(const fdw_layout &L, int ndim) {
+    fdw::Geom g{};
+    g.nx = (int)L.shape[0];
+    g.ny = ndim == 3 ? (int)L.shape[1] : 1;
+    g.nz = ndim == 3 ? (int)L.shape[2] : (int)L.shape[1];
+    g.sy = ndim == 3 ? L.pitch_x : 0;
+    g.sz = ndim == 3 ? L.pitch_x * L.pitch_y : L.pitch_x;
+    g.off0 = L.origin_offset;
+    return g;
+}
+
+// logical host array (x fastest) -> padded device slot: one contiguous copy
+// into a device staging buffer, then a scatter kernel into the layout
+int upload_field(const fdw_layout &L, int ndim, const float *host, float *staging, float *dev, hipStream_t s) {
+    const fdw::Geom g = layout_geom(L, ndim);
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    hipError_t e = hipMemcpyAsync(staging, host, n * sizeof(float), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = fdw::launch_pad_copy(g, staging, dev, s);
+    if (e != hipSuccess) return sfail_hip(e, "server: model upload");
     return FDW_OK;
 }
 
@@ -302,6 +308,16 @@ int admit(fdw_server *sv, Shot *s) {
     }
     const float *params[5] = {d.m, d.eps, d.delta, d.theta, d.phi};
     static const char *pname[5] = {"m", "eps", "delta", "theta", "phi"};
+    size_t nlog = 1;
+    for (int a = 0; a < d.ndim; ++a) nlog *= (size_t)d.shape[a];
+    void *staging = nullptr;
+    if ((st = pool_alloc(sv, sizeof(float) * nlog, &staging))) return fail_admit(st);
+    struct StagingGuard {  // back to the pool once the uploads are done
+        fdw_server *sv;
+        void *p;
+        size_t n;
+        ~StagingGuard() { pool_release(sv, p, n); }
+    } guard{sv, staging, sizeof(float) * nlog};
     for (int k = 0; k < z.nparam; ++k) {
         if (!params[k]) return fail_admit(sfail(FDW_ERR_ARG, "server: ticket %lld: %s missing", (long long)s->ticket, pname[k]));
         void *p = nullptr;
@@ -310,7 +326,10 @@ int admit(fdw_server *sv, Shot *s) {
         const uint32_t fill = k == 0 ? 0x3f800000u : 0u;
         hipError_t e = hipMemsetD32Async((hipDeviceptr_t)p, (int)fill, (size_t)E, hs);
         if (e != hipSuccess) return fail_admit(sfail_hip(e, "server: parameter fill"));
-        if ((st = upload_field(s->lay, d.ndim, params[k], (float *)p, hs))) return fail_admit(st);
+        if ((st = upload_field(s->lay, d.ndim, params[k], (float *)staging, (float *)p, hs))) return fail_admit(st);
+        // the staging buffer is reused by the next field
+        hipError_t es = hipStreamSynchronize(hs);
+        if (es != hipSuccess) return fail_admit(sfail_hip(es, "server: upload"));
         st = fdw_function_bind(s->grid, pname[k], (float *)p, E, d.space_order, &s->fn[k]);
         if (st) return fail_admit(lib_fail(st, "server: parameter"));
     }
@@ -527,7 +546,9 @@ int fdw_server_progress(fdw_server *sv, int *queued, int *running) {
             ++it;
             continue;
         }
+        const double ta = sv->now();
         int st = admit(sv, s);
+        sv->admit_s += sv->now() - ta;
         if (st == FDW_ERR_NOMEM && (!sv->pool.empty() || !sv->graveyard.empty())) {
             // free cached blocks and retired objects, then try once more
             for (auto &kv : sv->buckets)
@@ -548,7 +569,9 @@ int fdw_server_progress(fdw_server *sv, int *queued, int *running) {
     for (auto &kv : sv->buckets) {
         Bucket *b = kv.second.get();
         if (!b->active.empty() && b->inflight.size() < 2) {
+            const double tl = sv->now();
             int st = launch_chunk(sv, b);
+            sv->launch_s += sv->now() - tl;
             if (st) return st;
         }
         nrun += (int)b->active.size();
@@ -634,6 +657,8 @@ int fdw_server_stats(fdw_server *sv, fdw_server_stats_t *out) {
     out->graph_builds = builds;
     out->graph_launches = launches;
     out->now = sv->now();
+    out->admit_seconds = sv->admit_s;
+    out->launch_seconds = sv->launch_s;
     return FDW_OK;
 }
 

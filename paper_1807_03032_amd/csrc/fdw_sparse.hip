@@ -85,6 +85,16 @@ __global__ void __launch_bounds__(256) zero_halo_kernel(int ndim, Geom g, int R,
     if (!inside) base[e] = 0.0f;
 }
 
+// Logical array (x fastest, no halo) into the domain of a padded slot: one
+// thread per logical element, x in a workgroup row.
+__global__ void __launch_bounds__(256) pad_copy_kernel(Geom g, const float *__restrict__ src, float *dst) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int row = blockIdx.y * 4 + (threadIdx.x >> 6);  // y + ny * z
+    if (x >= g.nx || row >= g.ny * g.nz) return;
+    const int y = row % g.ny, z = row / g.ny;
+    dst[g.off0 + (int64_t)z * g.sz + (int64_t)y * g.sy + x] = src[(int64_t)row * g.nx + x];
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -131,6 +141,13 @@ hipError_t launch_zero_halo(int ndim, const Geom &g, int R, int64_t pitch_x, int
     const int64_t total = pitch_x * pitch_y * planes;
     hipLaunchKernelGGL(zero_halo_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ndim, g, R,
                        pitch_x, pitch_y, planes, base);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_copy(const Geom &g, const float *src, float *dst, hipStream_t s) {
+    const int64_t rows = (int64_t)g.ny * g.nz;
+    hipLaunchKernelGGL(pad_copy_kernel, dim3((unsigned)((g.nx + 63) / 64), (unsigned)((rows + 3) / 4)), dim3(256), 0,
+                       s, g, src, dst);
     return hipGetLastError();
 }
 

@@ -90,7 +90,7 @@ class fdw_server_stats_t(ctypes.Structure):
     _fields_ = [("budget", ctypes.c_int64), ("used", ctypes.c_int64), ("pool_bytes", ctypes.c_int64),
                 ("chunks", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("buckets", ctypes.c_int64), ("graph_builds", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
-                ("now", ctypes.c_double)]
+                ("now", ctypes.c_double), ("admit_seconds", ctypes.c_double), ("launch_seconds", ctypes.c_double)]
 
 
 _lib = None
