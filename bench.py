@@ -70,8 +70,8 @@ def time_shot(prob, steps, warmup, device, nslots=3, timing_every=10):
     for t in shot.wave.values():
         t.zero_()
     shot.rec_data.zero_()
-    # HIP events on one stencil launch in every `timing_every` (each bracketed
-    # launch costs the stream a few microseconds)
+    # HIP events around runs of `timing_every` consecutive stencil launches
+    # (every launch covered; the events' own few microseconds spread over a run)
     fdw.fdw_operator_set_timing(shot.op, timing_every)
     torch.cuda.synchronize(device)
     t0 = time.perf_counter()

@@ -333,14 +333,16 @@ int fdw_server_release(fdw_server *sv, int64_t ticket);
 int fdw_server_stats(fdw_server *sv, fdw_server_stats_t *out);
 int fdw_server_destroy(fdw_server *sv);
 
-/* Per-kernel timing (measurement support).  enable = k > 0 brackets one launch
- * in every k of the operator's dominant stencil kernel (counting from the first
- * launch after this call; k = 1: every launch) with a pair of HIP events on the
- * apply stream; 0 disables.  Events cost the stream a few microseconds per
- * bracketed launch, so sampling keeps that cost out of a timed loop.
- * fdw_operator_kernel_time synchronises and returns the summed milliseconds and
- * the number of bracketed launches since the last reset.
- * Errors: FDW_ERR_ARG (NULL op, k < 0), FDW_ERR_DEVICE. */
+/* Per-kernel timing (measurement support).  enable = k > 0 times the launches
+ * of the operator's dominant stencil kernel in runs of k consecutive launches:
+ * the first launch of a run carries a HIP start event and the last a stop
+ * event, on the apply stream (an apply that ends inside a run closes it with
+ * an event after its last launch); 0 disables.  Every launch is covered; the
+ * per-launch average includes the (small) gaps between the launches of a run
+ * and 1/k of the events' own cost of a few microseconds.  k = 1 brackets each
+ * launch alone.  fdw_operator_kernel_time synchronises and returns the summed
+ * milliseconds of all runs and the number of launches they cover since the
+ * last reset.  Errors: FDW_ERR_ARG (NULL op, k < 0), FDW_ERR_DEVICE. */
 int fdw_operator_set_timing(fdw_op *op, int enable);
 int fdw_operator_kernel_time(fdw_op *op, double *total_ms, int64_t *launches, int reset);
 

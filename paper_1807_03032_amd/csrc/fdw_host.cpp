@@ -126,8 +126,10 @@ struct fdw_op {
     bool src_fused = false;
     // timing
     bool timing = false;
-    int timing_every = 1;    // one stencil launch in every timing_every carries events
-    int64_t timing_seq = 0;  // stencil launches since timing was enabled
+    int timing_every = 1;    // launches per timed run
+    int run_len = 0;         // launches in the open run
+    bool run_open = false;
+    hipEvent_t run_start = nullptr, run_stop = nullptr;
     std::vector<hipEvent_t> ev_pool;  // pairs
     size_t ev_used = 0;
     double acc_ms = 0.0;
@@ -860,6 +862,35 @@ static int timing_event_pair(fdw_op *op, hipEvent_t *a, hipEvent_t *b) {
     return FDW_OK;
 }
 
+// Events of the next stencil launch: runs of timing_every consecutive
+// launches, the first carrying the start event and the last the stop event.
+static int timing_next(fdw_op *op, LaunchEvents &ev) {
+    if (!op->timing) return FDW_OK;
+    if (!op->run_open) {
+        int st = timing_event_pair(op, &op->run_start, &op->run_stop);
+        if (st) return st;
+        ev.start = op->run_start;
+        op->run_open = true;
+        op->run_len = 0;
+    }
+    if (++op->run_len == op->timing_every) {
+        ev.stop = op->run_stop;
+        op->run_open = false;
+        op->acc_launches += op->run_len;
+    }
+    return FDW_OK;
+}
+
+// an apply that ends inside a run closes it after its last launch
+static int timing_close(fdw_op *op, hipStream_t s) {
+    if (!op->timing || !op->run_open) return FDW_OK;
+    hipError_t e = hipEventRecord(op->run_stop, s);
+    if (e != hipSuccess) return fail_hip(e, "operator_apply: timing event");
+    op->run_open = false;
+    op->acc_launches += op->run_len;
+    return FDW_OK;
+}
+
 int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
     FDW_GUARD_BEGIN
     if (!op) return fail(FDW_ERR_ARG, "operator_apply: NULL op");
@@ -912,15 +943,11 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         pa.rec_w = op->d_rec_w;
         pa.rec_data = nrec > 0 ? d.rec->data : nullptr;
         LaunchEvents ev;
-        const bool timed = op->timing && op->timing_seq++ % op->timing_every == 0;
-        if (timed) {
-            int st = timing_event_pair(op, &ev.start, &ev.stop);
-            if (st) return st;
-        }
+        int st = timing_next(op, ev);
+        if (st) return st;
         hipError_t e = launch_iso2d_persistent(op->R, pa, s, ev);
         if (e != hipSuccess) return fail_hip(e, "operator_apply: persistent 2D launch");
-        if (timed) op->acc_launches++;
-        return FDW_OK;
+        return timing_close(op, s);
     }
     const int S_ring = d.u->nslots + 1;
     // the 3D streaming kernels sample the receivers of step t - 1 inside the
@@ -944,11 +971,7 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         }
         const int sn = (t + 1) % d.u->nslots;
         LaunchEvents ev;
-        const bool timed = op->timing && op->timing_seq++ % op->timing_every == 0;
-        if (timed) {
-            int st = timing_event_pair(op, &ev.start, &ev.stop);
-            if (st) return st;
-        }
+        if (int st = timing_next(op, ev)) return st;
         hipError_t e;
         float *next_field;
         float *save_dst = nullptr;
@@ -984,7 +1007,6 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             next_field = a.p_next;
         }
         if (e != hipSuccess) return fail_hip(e, "operator_apply: stencil launch");
-        if (timed) op->acc_launches++;
         if (nsrc > 0 && !op->src_fused) {
             inj.q_row = d.src->data + (int64_t)t * nsrc;
             inj.field = next_field;
@@ -1013,6 +1035,7 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             }
         }
     }
+    if (int st = timing_close(op, s)) return st;
     // the caller's stream covers every receiver sample of this apply
     if (op->overlap_interp && nrec > 0 && time_M >= time_m) {
         const int last = std::max(time_m, time_M - d.u->nslots + 1);
@@ -1068,7 +1091,8 @@ int fdw_operator_set_timing(fdw_op *op, int enable) {
     if (enable < 0) return fail(FDW_ERR_ARG, "set_timing: negative sampling interval %d", enable);
     op->timing = enable != 0;
     op->timing_every = enable > 0 ? enable : 1;
-    op->timing_seq = 0;
+    op->run_open = false;
+    op->run_len = 0;
     op->ev_used = 0;
     op->acc_ms = 0.0;
     op->acc_launches = 0;

@@ -270,7 +270,7 @@ def fdw_gradient_accumulate(op, nu: int, u_next: int, u_cur: int, u_prev: int, g
 
 
 def fdw_operator_set_timing(op, enable):
-    """enable: False/0 off, True/1 every launch, k > 1 one launch in every k."""
+    """enable: False/0 off, True/1 each launch bracketed alone, k > 1 runs of k consecutive launches."""
     _chk(load().fdw_operator_set_timing(op, int(enable)))
 
 

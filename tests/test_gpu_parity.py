@@ -300,3 +300,25 @@ def test_inplace_two_slot_storage(torch_dev, kind, shape, so):
     for nm in gf:
         np.testing.assert_array_equal(gf[nm][1], gfs[nm][1])
     np.testing.assert_array_equal(gtr, gtrs)
+
+
+def test_kernel_timing_covers_every_launch(torch_dev):
+    """Timed runs of k consecutive stencil launches cover every launch, also
+    when an apply ends inside a run."""
+    from paper_1807_03032_amd import fdw
+    prob = W.small_problem("iso", (40, 36, 30), 8, nt=10, seed=3)
+    shot = fdw.Shot(prob, torch_dev, nslots=2)
+    try:
+        for k in (1, 4):
+            fdw.fdw_operator_set_timing(shot.op, k)
+            shot.apply(0, 9)
+            ms, n = fdw.fdw_operator_kernel_time(shot.op)
+            assert n == 10 and ms > 0
+        fdw.fdw_operator_set_timing(shot.op, 3)
+        shot.apply(0, 4)
+        shot.apply(5, 9)
+        ms, n = fdw.fdw_operator_kernel_time(shot.op)
+        assert n == 10 and ms > 0
+        fdw.fdw_operator_set_timing(shot.op, 0)
+    finally:
+        shot.close()
