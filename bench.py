@@ -47,6 +47,9 @@ def parse():
                          "p50/p99 latency and aggregate GPts/s against sequential per-shot solves")
     ap.add_argument("--serve-count", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=3.0, help="mean request arrivals per second")
+    ap.add_argument("--tb2d", action="store_true",
+                    help="also time the 2D temporal blocking (steps per launch on LDS patches) against one "
+                         "launch per step on a 2D 8001^2 so=8 grid")
     ap.add_argument("--save-every", type=int, default=0,
                     help="also time the isotropic workload while saving every k-th level (snapshots)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -113,6 +116,39 @@ def snapshot_leg(prob, every, device):
     return {"every": every, "levels": nlev, "buffer_gib": round(nlev * shot.lay.elems_per_slot * 4 / 2 ** 30, 2),
             "value": round(prob.npoints * prob.nt / wall / 1e9, 3), "unit": "GPts/s",
             "ms_per_step": round(wall * 1e3 / prob.nt, 5)}
+
+
+def tb2d_leg(device, n=8001, so=8, nt=200):
+    """2D isotropic n^2, so, nt steps, two-slot storage: temporal blocking
+    (several steps per launch, FDW_TB=1) against one launch per step."""
+    import torch
+
+    from paper_1807_03032_amd import fdw
+    from paper_1807_03032_amd import workloads as W
+
+    prob = W.small_problem("iso", (n, n), so, nt=nt, seed=5, nsrc=1, nrec=n, nbl=40)
+    out = {"workload": f"2D isotropic {n}^2, so={so}, {nt} steps, 1 source, {n} receivers, two-slot storage"}
+    for label, env in (("temporal_blocking", "1"), ("per_step", "0")):
+        os.environ["FDW_TB"] = env
+        shot = fdw.Shot(prob, device, nslots=2)
+        try:
+            shot.apply(0, 9)
+            torch.cuda.synchronize(device)
+            fdw.fdw_operator_set_timing(shot.op, 10)
+            t0 = time.perf_counter()
+            shot.apply(0, nt - 1)
+            torch.cuda.synchronize(device)
+            wall = time.perf_counter() - t0
+            kms, launches = fdw.fdw_operator_kernel_time(shot.op)
+            desc = fdw.fdw_operator_describe(shot.op)[0]
+        finally:
+            shot.close()
+        out[label] = {"kernel": desc, "value": round(prob.npoints * nt / wall / 1e9, 2), "unit": "GPts/s",
+                      "ms_per_step": round(wall * 1e3 / nt, 4), "launches": launches,
+                      "kernel_avg_us": round(kms * 1e3 / max(launches, 1), 2)}
+    os.environ.pop("FDW_TB", None)
+    out["speedup"] = round(out["temporal_blocking"]["value"] / out["per_step"]["value"], 2)
+    return out
 
 
 def run_server(reqs, arrivals, chunk_us=20000, nstreams=4):
@@ -489,6 +525,8 @@ def main():
         line["adjoint"] = adjoint_leg(dev)
     if args.save_every > 0:
         line["snapshots"] = snapshot_leg(prob, args.save_every, dev)
+    if args.tb2d:
+        line["tb2d"] = tb2d_leg(dev)
     if args.serve:
         line["serve"] = serve_leg(dev, args.serve_count, args.serve_rate)
         line["serve_fused_burst"] = fused_burst_leg(dev)

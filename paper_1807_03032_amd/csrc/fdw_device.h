@@ -61,18 +61,28 @@ __device__ __forceinline__ float laplacian_at(const float *u, int64_t i, const G
 
 // Fused injection for the point (x, y, z): adds dt^2 w_c q_s / m (times scale)
 // for every fused source s whose interpolation cell has this point as corner c.
-__device__ __forceinline__ float fused_inject(const FusedSrc &src, int ndim, int x, int y, int z,
+// (q: this step's samples; the overload below takes them from src.q)
+__device__ __forceinline__ float fused_inject(const FusedSrc &src, const float *q, int ndim, int x, int y, int z,
                                               float rcp_m, float val, float scale = 1.0f) {
+    // every product and sum rounded on its own: the result does not depend on
+    // whether the compiler can see that scale is 1 (kernels that inline this
+    // with a constant or a run-time scale give the same bits)
+#pragma clang fp contract(off)
     for (int s = 0; s < src.n; ++s) {
         const unsigned dx = (unsigned)(x - src.bx[s]);
         const unsigned dy = (unsigned)(y - src.by[s]);
         const unsigned dz = (unsigned)(z - src.bz[s]);
         if (dx <= 1u && dy <= 1u && dz <= 1u) {
             const int c = ndim == 3 ? (int)(dx + 2u * dy + 4u * dz) : (int)(dx + 2u * dz);
-            val += src.w[s][c] * src.q[s] * rcp_m * scale;
+            val += src.w[s][c] * q[s] * rcp_m * scale;
         }
     }
     return val;
+}
+
+__device__ __forceinline__ float fused_inject(const FusedSrc &src, int ndim, int x, int y, int z,
+                                              float rcp_m, float val, float scale = 1.0f) {
+    return fused_inject(src, src.q, ndim, x, y, z, rcp_m, val, scale);
 }
 
 __device__ __forceinline__ float damp_at(const float *ex, const float *ey, const float *ez, int ndim,

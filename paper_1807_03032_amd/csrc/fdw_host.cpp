@@ -111,6 +111,8 @@ struct fdw_op {
     IsoVariant iso_v = IsoVariant::Naive;
     TtiVariant tti_v = TtiVariant::Naive;
     bool use_persist2d = false;  // 2D iso grid small enough for the LDS-resident kernel
+    bool use_tb2d = false;       // 2D iso: K steps per launch on overlapped LDS patches
+    float *d_tb = nullptr;       // temporal blocking: second pair of level buffers
     // library-owned device memory
     float *d_eta = nullptr;           // eta_x | eta_y | eta_z (times dt/2)
     float *d_stage = nullptr;         // TTI: gp | gr (each elems_per_slot)
@@ -456,6 +458,8 @@ int fdw_sparse_destroy(fdw_sparse *s) {
 static void release_device(fdw_op *op) {
     if (op->d_eta) (void)hipFree(op->d_eta);
     if (op->d_stage) (void)hipFree(op->d_stage);
+    if (op->d_tb) (void)hipFree(op->d_tb);
+    op->d_tb = nullptr;
     if (op->d_src_base) (void)hipFree(op->d_src_base);
     if (op->d_rec_base) (void)hipFree(op->d_rec_base);
     if (op->d_src_w) (void)hipFree(op->d_src_w);
@@ -709,6 +713,28 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
     }
 
     pick_variants(op);
+    // 2D isotropic grids too large for the LDS-resident kernel can advance K
+    // steps per launch on overlapped patches (opt-in, FDW_TB=1: on one MI355X
+    // the per-step kernel, served from the Infinity Cache, is faster at the
+    // sizes measured); in-place two-slot storage, fused (or no) sources,
+    // linear receivers
+    {
+        const char *tb = std::getenv("FDW_TB");
+        const bool off = !(tb && tb[0] == '1') || op->iso_v == IsoVariant::Naive;
+        op->use_tb2d = !off && d.kind == FDW_ISO && op->ndim == 2 && d.mode == FDW_FORWARD && !op->use_persist2d &&
+                       d.u->nslots == 2 && (!d.src || d.src->npoint == 0 || op->src_fused) &&
+                       (!d.rec || d.rec->npoint == 0 || d.rec->r == 2) && tb2d_shape(op->R).k > 0;
+        if (op->use_tb2d) {
+            const size_t bytes = sizeof(float) * (size_t)L.elems_per_slot * 2;
+            hipError_t e2 = hipMalloc((void **)&op->d_tb, bytes);
+            if (e2 == hipSuccess) e2 = hipMemset(op->d_tb, 0, bytes);
+            if (e2 != hipSuccess) {
+                release_device(op);
+                delete op;
+                return fail(FDW_ERR_NOMEM, "operator_create: level buffers: %s", hipGetErrorString(e2));
+            }
+        }
+    }
     // Receiver sampling of step t reads level t+1, which the stencil of step
     // t + S (S = slots) overwrites: it can run on a second stream, overlapped with
     // the next stencil launches, ordered by events (opt-in, FDW_OVERLAP_INTERP=1:
@@ -949,6 +975,54 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         if (e != hipSuccess) return fail_hip(e, "operator_apply: persistent 2D launch");
         return timing_close(op, s);
     }
+    // 2D temporal blocking: passes of up to K steps, each reading its two input
+    // levels from one pair of buffers and writing its two output levels to the
+    // other; the pass count fixes which pair the first pass reads so that the
+    // last pass writes the TimeFunction's slots (level k in slot k mod 2)
+    if (op->use_tb2d && !op->save_buf && time_M >= time_m) {
+        const TB2DShape sh = tb2d_shape(op->R);
+        const int N = time_M - time_m + 1, P = (N + sh.k - 1) / sh.k;
+        float *tfb = d.u->d, *scb = op->d_tb;
+        float *X = tfb, *Y = scb;
+        if (P % 2 == 1) {
+            hipError_t e = hipMemcpyAsync(scb, tfb, sizeof(float) * 2 * (size_t)E, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return fail_hip(e, "operator_apply: level copy");
+            X = scb;
+            Y = tfb;
+        }
+        for (int t0 = time_m; t0 <= time_M; t0 += sh.k) {
+            const int n = std::min(sh.k, time_M - t0 + 1);
+            TB2DArgs a{};
+            a.g = op->geom;
+            a.in_prev = X + (int64_t)((t0 + 1) % 2) * E;  // level t0 - 1
+            a.in_cur = X + (int64_t)(t0 % 2) * E;
+            a.out_prev = Y + (int64_t)((t0 + n + 1) % 2) * E;  // level t0 + n - 1
+            a.out_cur = Y + (int64_t)((t0 + n) % 2) * E;
+            a.m = d.m->d;
+            a.eta_x = eta_x;
+            a.eta_z = eta_z;
+            a.dt2 = op->dt2;
+            a.c = op->coefs;
+            if (op->src_fused && nsrc > 0) {
+                a.src = op->fsrc_template;
+                a.src.q = d.src->data + (int64_t)t0 * nsrc;
+                a.src_stride = nsrc;
+            }
+            a.nsteps = n;
+            a.nrec = nrec;
+            if (nrec > 0) {
+                a.rec_idx = op->d_rec_idx;
+                a.rec_w = op->d_rec_w;
+                a.rec_rows = d.rec->data + (int64_t)t0 * nrec;
+            }
+            LaunchEvents ev;
+            if (int st = timing_next(op, ev)) return st;
+            hipError_t e = launch_iso2d_tb(op->R, a, s, ev);
+            if (e != hipSuccess) return fail_hip(e, "operator_apply: temporal-blocking launch");
+            std::swap(X, Y);
+        }
+        return timing_close(op, s);
+    }
     const int S_ring = d.u->nslots + 1;
     // the 3D streaming kernels sample the receivers of step t - 1 inside the
     // launch of step t (extra workgroups reading level t); the last step of the
@@ -1125,7 +1199,14 @@ int fdw_operator_kernel_time(fdw_op *op, double *total_ms, int64_t *launches, in
 int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_bytes_per_point) {
     if (!op || !buf || buflen <= 0) return fail(FDW_ERR_ARG, "describe: NULL argument");
     const bool iso = op->d.kind == FDW_ISO;
+    char tbname[96];
+    if (op->use_tb2d) {
+        const TB2DShape sh = tb2d_shape(op->R);
+        snprintf(tbname, sizeof(tbname), "iso2d_tb (temporal blocking, %d steps per launch, tile %dx%d)", sh.k, sh.ix,
+                 sh.iz);
+    }
     const char *name = iso ? (op->use_persist2d ? "iso2d_persistent (LDS-resident, one launch per apply)"
+                              : op->use_tb2d    ? tbname
                                                 : iso_kernel_name(op->ndim, op->iso_v))
                            : tti_kernel_name(op->ndim, op->tti_v);
     snprintf(buf, (size_t)buflen, "%s so=%d R=%d ndim=%d src=%s nsrc=%d nrec=%d", name, op->d.space_order, op->R,

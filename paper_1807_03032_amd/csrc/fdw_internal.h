@@ -145,6 +145,35 @@ struct Persist2DArgs {
     float *rec_data;        // [nt][nrec]
 };
 
+// Temporal blocking of the 2D isotropic step: every workgroup advances an
+// overlapped patch (its inner tile plus a halo of K R + 1 points) by up to K
+// steps in LDS, then writes the inner tile's last two levels.  Reads and
+// writes go to different buffers (levels are read from in_*, written to
+// out_*), so one launch needs no grid-wide synchronisation.
+struct TB2DArgs {
+    Geom g;
+    const float *in_prev, *in_cur;  // levels t0 - 1, t0
+    float *out_prev, *out_cur;      // levels t0 + nsteps - 1, t0 + nsteps (inner tiles)
+    const float *m;
+    const float *eta_x, *eta_z;
+    float dt2;
+    Coefs c;
+    FusedSrc src;                   // src.q: samples of step t0
+    int src_stride;                 // samples per step (row stride of src.q)
+    int nsteps;                     // 1 .. K
+    int nrec;
+    const int *rec_idx;             // [nrec][3] base grid indices (x, 0, z)
+    const float *rec_w;             // [nrec][4]
+    float *rec_rows;                // row of step t0 (row stride nrec)
+};
+
+// steps per pass and inner tile of the 2D temporal blocking at radius R
+struct TB2DShape {
+    int k, ix, iz;
+};
+TB2DShape tb2d_shape(int R);
+size_t tb2d_lds_bytes(int R);
+
 // Largest LDS footprint (bytes) the persistent 2D kernel may use.
 constexpr int kPersist2DMaxLds = 152 * 1024;
 
@@ -166,6 +195,7 @@ hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream
 hipError_t launch_inject(const SparseArgs &a, hipStream_t s);
 hipError_t launch_interp(const SparseArgs &a, hipStream_t s);
 hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s, const LaunchEvents &ev);
+hipError_t launch_iso2d_tb(int R, const TB2DArgs &a, hipStream_t s, const LaunchEvents &ev);
 // grad += -nu [(u+ - 2u + u-)/dt^2 + eta (u+ - u-)/(2 dt)] over the domain
 struct GradArgs {
     Geom g;
