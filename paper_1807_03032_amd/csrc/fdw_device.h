@@ -8,6 +8,7 @@
 #pragma once
 #include "fdw_internal.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -224,7 +225,11 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
     // workgroups past the stencil tiles sample the receivers of the previous
     // step from the current level, which this launch only reads
     if (bid >= nb_stencil) {
-        interp_lane(sp, (bid - nb_stencil) * NT + (int)threadIdx.x);
+        // a few workgroups loop over the receivers (groups of ncorner lanes
+        // stay together, so the shuffles always find their partners)
+        const int stride = ((int)gridDim.x - nb_stencil) * NT;
+        const int lanes = sp.npoint * sp.ncorner;
+        for (int l = (bid - nb_stencil) * NT + (int)threadIdx.x; l < lanes; l += stride) interp_lane(sp, l);
         return;
     }
     if (!stencil_live) return;
@@ -427,6 +432,17 @@ __global__ void __launch_bounds__(64 * BY) stream3d_multi(const StreamShot<Op, N
                                          S.live != 0);
 }
 
+// Workgroups that sample receivers inside a streaming launch (each loops over
+// its share; FDW_INTERP_WG overrides the default for tuning).
+static inline int64_t interp_workgroups() {
+    static const int64_t n = [] {
+        const char *e = std::getenv("FDW_INTERP_WG");
+        const long v = e ? std::strtol(e, nullptr, 10) : 0;
+        return (int64_t)(v > 0 ? v : 1024);
+    }();
+    return n;
+}
+
 // Fused launch of n same-geometry shots (records in device memory); rec_lanes
 // = the largest npoint * ncorner of the shots' receiver rows.
 template <int R, int NY, int PF, int BY, int NQ, int NP, class Op>
@@ -436,7 +452,7 @@ static hipError_t launch_stream3d_multi(const StreamShot<Op, NQ, NP> *shots, int
     if (zc > g.nz) zc = g.nz;
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + BY * NY - 1) / (BY * NY), ntz = (g.nz + zc - 1) / zc;
     const int64_t nb = (int64_t)ntx * nty * ntz;
-    const int64_t ni = (rec_lanes + 64 * BY - 1) / (64 * BY);
+    const int64_t ni = std::min<int64_t>((rec_lanes + 64 * BY - 1) / (64 * BY), interp_workgroups());
     hipLaunchKernelGGL((stream3d_multi<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)(nb + ni), (unsigned)n),
                        dim3(64 * BY), 0, s, shots, g, zc, ntx, nty, 0, (int)nb);
     return hipGetLastError();
@@ -467,7 +483,7 @@ static hipError_t launch_stream3d(const Op &op, const StreamFields<NQ, NP> &F, c
     int64_t ni = 0;  // extra workgroups for receiver sampling
     if (sp && sp->npoint > 0) {
         spv = *sp;
-        ni = ((int64_t)sp->npoint * sp->ncorner + 64 * BY - 1) / (64 * BY);
+        ni = std::min<int64_t>(((int64_t)sp->npoint * sp->ncorner + 64 * BY - 1) / (64 * BY), interp_workgroups());
     }
     // tile order: FDW_TILE_ORDER=z puts the z-chunk index fastest (tuning knob)
     const char *order = std::getenv("FDW_TILE_ORDER");

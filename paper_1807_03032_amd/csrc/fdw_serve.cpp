@@ -96,6 +96,7 @@ struct Shot {
     float *h_rec = nullptr;
     float *h_field = nullptr;  // padded last level of u / p when kept
     Bucket *bucket = nullptr;
+    bool released = false;     // results fetched; freed with the graveyard
 };
 
 }  // namespace
@@ -176,8 +177,19 @@ void destroy_objects(Shot *s) {
     s->grid = nullptr;
 }
 
+// Library objects and pinned buffers of retired shots are freed only here
+// (hipFree / hipHostFree wait for the device), when the server is idle or
+// short of memory, and at destruction.
 void flush_graveyard(fdw_server *sv) {
-    for (Shot *s : sv->graveyard) destroy_objects(s);
+    for (Shot *s : sv->graveyard) {
+        destroy_objects(s);
+        if (s->released) {
+            if (s->h_rec) (void)hipHostFree(s->h_rec);
+            if (s->h_field) (void)hipHostFree(s->h_field);
+            s->h_rec = s->h_field = nullptr;
+            sv->shots.erase(s->ticket);
+        }
+    }
     sv->graveyard.clear();
 }
 
@@ -586,7 +598,8 @@ int fdw_server_progress(fdw_server *sv, int *queued, int *running) {
 int fdw_server_info(fdw_server *sv, int64_t ticket, fdw_shot_info *out) {
     if (!sv || !out) return sfail(FDW_ERR_ARG, "server_info: NULL argument");
     auto it = sv->shots.find(ticket);
-    if (it == sv->shots.end()) return sfail(FDW_ERR_ARG, "server_info: unknown ticket %lld", (long long)ticket);
+    if (it == sv->shots.end() || it->second->released)
+        return sfail(FDW_ERR_ARG, "server_info: unknown or released ticket %lld", (long long)ticket);
     const Shot *s = it->second.get();
     out->state = s->state;
     out->footprint = s->footprint;
@@ -603,6 +616,7 @@ int fdw_server_fetch(fdw_server *sv, int64_t ticket, float *rec_host, float *fie
     if (it == sv->shots.end()) return sfail(FDW_ERR_ARG, "server_fetch: unknown ticket %lld", (long long)ticket);
     Shot *s = it->second.get();
     if (s->state != FDW_SHOT_DONE) return sfail(FDW_ERR_STATE, "server_fetch: ticket %lld not finished", (long long)ticket);
+    if (s->released) return sfail(FDW_ERR_STATE, "server_fetch: ticket %lld was released", (long long)ticket);
     const fdw_shot_desc &d = s->d;
     if (rec_host && d.nrec > 0) std::memcpy(rec_host, s->h_rec, sizeof(float) * (size_t)d.nt * d.nrec);
     if (field_host) {
@@ -625,14 +639,14 @@ int fdw_server_release(fdw_server *sv, int64_t ticket) {
     if (it == sv->shots.end()) return sfail(FDW_ERR_ARG, "server_release: unknown ticket %lld", (long long)ticket);
     Shot *s = it->second.get();
     if (s->state != FDW_SHOT_DONE) return sfail(FDW_ERR_STATE, "server_release: ticket %lld not finished", (long long)ticket);
-    auto g = std::find(sv->graveyard.begin(), sv->graveyard.end(), s);
-    if (g != sv->graveyard.end()) {
-        destroy_objects(s);
-        sv->graveyard.erase(g);
+    if (s->released) return sfail(FDW_ERR_STATE, "server_release: ticket %lld already released", (long long)ticket);
+    s->released = true;
+    // freeing now would wait for the device: the graveyard frees it later
+    if (std::find(sv->graveyard.begin(), sv->graveyard.end(), s) == sv->graveyard.end()) {
+        if (s->h_rec) (void)hipHostFree(s->h_rec);
+        if (s->h_field) (void)hipHostFree(s->h_field);
+        sv->shots.erase(it);
     }
-    if (s->h_rec) (void)hipHostFree(s->h_rec);
-    if (s->h_field) (void)hipHostFree(s->h_field);
-    sv->shots.erase(it);
     return FDW_OK;
 }
 
@@ -683,6 +697,7 @@ int fdw_server_destroy(fdw_server *sv) {
         Shot *s = kv.second.get();
         if (s->h_rec) (void)hipHostFree(s->h_rec);
         if (s->h_field) (void)hipHostFree(s->h_field);
+        s->h_rec = s->h_field = nullptr;
     }
     pool_trim(sv);
     for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
