@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps of the bounded CPU sample")
     ap.add_argument("--tti", action="store_true", help="also time the 512^3 TTI so=12 operator")
+    ap.add_argument("--tti-n", type=int, default=512, help="grid points per axis of the TTI leg (512: the workload)")
+    ap.add_argument("--tti-steps", type=int, default=0, help="steps of the TTI leg (0: the workload's 800)")
     ap.add_argument("--nslots", type=int, default=2, choices=(2, 3),
                     help="wavefield storage of the isotropic workload: 2 = in-place leapfrog (default), "
                          "3 = modulo-3 buffer u[t %% 3]")
@@ -59,7 +61,7 @@ def parse():
     return ap.parse_args()
 
 
-def time_shot(prob, steps, warmup, device, nslots=3, timing_every=10):
+def time_shot(prob, steps, warmup, device, nslots=3, timing_every=50):
     """Warm up, reset to the zero initial state, then time `steps` time steps."""
     import torch
 
@@ -512,13 +514,13 @@ def main():
     if par is not None:
         line["parity_rel_l2_sampled"] = par
     if args.tti:
-        pt = W.config_3d_tti_512()
-        w2, k2, l2, d2, b2, tr2, f2 = time_shot(pt, pt.nt, 20, dev)
-        line["tti"] = {"workload": "3D TTI 512^3, h=12.5 m, so=12, nbl=40, 800 steps", "kernel": d2,
+        pt = W.config_3d_tti_512(nt=args.tti_steps or None, n=args.tti_n)
+        w2, k2, l2, d2, b2, tr2, f2 = time_shot(pt, pt.nt, min(20, pt.nt), dev)
+        line["tti"] = {"workload": f"3D TTI {args.tti_n}^3, h=12.5 m, so=12, nbl=40, {pt.nt} steps", "kernel": d2,
                        "value": round(pt.npoints * pt.nt / w2 / 1e9, 3), "unit": "GPts/s",
                        "roofline": roofline(pt, k2, l2, b2, load_traffic("tti", d2))}
         ops_seen.append({"desc": d2, "source_hash": source_hash("tti"), "kernel_match": ["TtiS1Op", "TtiS2Op", "tti_naive"]})
-        p2 = parity_vs_stored("3d_tti_512", pt, pt.nt, tr2, f2)
+        p2 = parity_vs_stored("3d_tti_512", pt, pt.nt, tr2, f2) if args.tti_n == 512 else None
         if p2 is not None:
             line["tti"]["parity_rel_l2_sampled"] = p2
     if args.adjoint:
