@@ -233,7 +233,10 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
         return;
     }
     if (!stencil_live) return;
-    constexpr int TX = 64, TY = BY * NY, LW = TX + 2 * R, LH = TY + 2 * R, Q = 2 * R + 1;
+    // LDS rows are padded to a multiple of 64 floats: the offset of a y
+    // neighbour is then a multiple of 256 bytes, which the paired LDS reads
+    // encode as an immediate (no per-neighbour address arithmetic)
+    constexpr int TX = 64, TY = BY * NY, LW = (TX + 2 * R + 63) / 64 * 64, LH = TY + 2 * R, Q = 2 * R + 1;
     constexpr int NHY = (2 * R + BY - 1) / BY;       // y-halo rows per wavefront
     constexpr int NHX = (TY * 2 * R + NT - 1) / NT;  // x-halo elements per thread
     __shared__ float lds[2][NQ][LH][LW];
