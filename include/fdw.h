@@ -278,12 +278,16 @@ int fdw_batch_destroy(fdw_batch *b);
  * all device memory (wavefields in two-slot in-place storage).  budget_bytes
  * <= 0 selects 80 % of the free device memory.  Single-threaded: calls on one
  * server must not overlap.
- * Errors: FDW_ERR_ARG, FDW_ERR_NOMEM (footprint above the budget at submit,
- * or allocation), FDW_ERR_STATE (fetch before completion), FDW_ERR_DEVICE,
- * and the operator-creation errors of a request (at its admission). */
+ * A request whose operator cannot be built (for instance dt above the
+ * stability bound), or that cannot be allocated even with nothing else
+ * resident, ends in state FDW_SHOT_FAILED instead of blocking the queue;
+ * fdw_server_fetch then returns FDW_ERR_STATE with the reason.
+ * Errors: FDW_ERR_ARG, FDW_ERR_NOMEM (footprint above the budget at submit),
+ * FDW_ERR_STATE (fetch before completion, failed shot), FDW_ERR_DEVICE. */
 #define FDW_SHOT_QUEUED 0
 #define FDW_SHOT_RUNNING 1
 #define FDW_SHOT_DONE 2
+#define FDW_SHOT_FAILED 3  /* rejected at admission (operator errors); see fdw_server_fetch */
 
 typedef struct {
     int kind;                  /* FDW_ISO or FDW_TTI                                     */

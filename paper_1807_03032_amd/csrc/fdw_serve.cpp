@@ -97,6 +97,7 @@ struct Shot {
     float *h_field = nullptr;  // padded last level of u / p when kept
     Bucket *bucket = nullptr;
     bool released = false;     // results fetched; freed with the graveyard
+    std::string error;         // why the shot failed at admission
 };
 
 }  // namespace
@@ -569,11 +570,16 @@ int fdw_server_progress(fdw_server *sv, int *queued, int *running) {
             pool_trim(sv);
             st = admit(sv, s);
         }
-        if (st == FDW_ERR_NOMEM) {
+        if (st == FDW_ERR_NOMEM && sv->used > 0) {  // may fit once running shots retire
             ++it;
             continue;
         }
-        if (st) return st;
+        if (st == FDW_ERR_DEVICE) return st;
+        if (st) {  // cannot be served: fail this request, keep serving the others
+            s->state = FDW_SHOT_FAILED;
+            s->error = fdw_last_error();
+            s->t_done = sv->now();
+        }
         it = sv->queue.erase(it);
     }
     // 3. next chunk of every bucket with running shots (two chunks in flight)
@@ -615,6 +621,9 @@ int fdw_server_fetch(fdw_server *sv, int64_t ticket, float *rec_host, float *fie
     auto it = sv->shots.find(ticket);
     if (it == sv->shots.end()) return sfail(FDW_ERR_ARG, "server_fetch: unknown ticket %lld", (long long)ticket);
     Shot *s = it->second.get();
+    if (s->state == FDW_SHOT_FAILED)
+        return sfail(FDW_ERR_STATE, "server_fetch: ticket %lld failed at admission: %s", (long long)ticket,
+                     s->error.c_str());
     if (s->state != FDW_SHOT_DONE) return sfail(FDW_ERR_STATE, "server_fetch: ticket %lld not finished", (long long)ticket);
     if (s->released) return sfail(FDW_ERR_STATE, "server_fetch: ticket %lld was released", (long long)ticket);
     const fdw_shot_desc &d = s->d;
@@ -638,7 +647,8 @@ int fdw_server_release(fdw_server *sv, int64_t ticket) {
     auto it = sv->shots.find(ticket);
     if (it == sv->shots.end()) return sfail(FDW_ERR_ARG, "server_release: unknown ticket %lld", (long long)ticket);
     Shot *s = it->second.get();
-    if (s->state != FDW_SHOT_DONE) return sfail(FDW_ERR_STATE, "server_release: ticket %lld not finished", (long long)ticket);
+    if (s->state != FDW_SHOT_DONE && s->state != FDW_SHOT_FAILED)
+        return sfail(FDW_ERR_STATE, "server_release: ticket %lld not finished", (long long)ticket);
     if (s->released) return sfail(FDW_ERR_STATE, "server_release: ticket %lld already released", (long long)ticket);
     s->released = true;
     // freeing now would wait for the device: the graveyard frees it later

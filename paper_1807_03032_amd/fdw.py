@@ -45,7 +45,7 @@ EXPORTS = (
     "fdw_server_create", "fdw_server_footprint", "fdw_server_submit", "fdw_server_progress", "fdw_server_info",
     "fdw_server_fetch", "fdw_server_release", "fdw_server_stats", "fdw_server_destroy",
 )
-FDW_SHOT_QUEUED, FDW_SHOT_RUNNING, FDW_SHOT_DONE = 0, 1, 2
+FDW_SHOT_QUEUED, FDW_SHOT_RUNNING, FDW_SHOT_DONE, FDW_SHOT_FAILED = 0, 1, 2, 3
 
 
 class FdwError(RuntimeError):

@@ -157,3 +157,42 @@ def test_server_keeps_within_budget(torch_dev):
         assert e.value.code == fdw.FDW_ERR_NOMEM
     finally:
         sv.close()
+
+
+def test_server_edge_requests(torch_dev):
+    """Requests without receivers, without sources, of a single step, and one
+    whose operator cannot be built (dt above the stability bound): the last
+    fails alone, the others are served."""
+    import dataclasses
+
+    from paper_1807_03032_amd import fdw
+    a = dataclasses.replace(W.serve_problem("iso", 2, 201, 8, 5, seed=50, nbl=10), rec_coords=np.zeros((0, 2)))
+    b0 = W.serve_problem("iso", 3, 40, 8, 1, seed=51, nbl=8)
+    b = dataclasses.replace(b0, src_coords=np.zeros((0, 3)), src=np.zeros((1, 0), dtype=np.float32))
+    c = dataclasses.replace(W.serve_problem("iso", 3, 40, 8, 10, seed=52, nbl=8), dt=3.0 * b0.dt)
+    d = W.serve_problem("tti", 2, 201, 4, 12, seed=53, nbl=10)
+    sv = fdw.Server(chunk_target_us=40, nstreams=2)
+    try:
+        tk = [sv.submit(p) for p in (a, b, c, d)]
+        deadline = time.time() + 60
+        final = (fdw.FDW_SHOT_DONE, fdw.FDW_SHOT_FAILED)
+        while not all(sv.info(t).state in final for t in tk):
+            assert time.time() < deadline
+            sv.progress()
+            time.sleep(1e-4)
+        states = [sv.info(t).state for t in tk]
+        assert states == [fdw.FDW_SHOT_DONE, fdw.FDW_SHOT_DONE, fdw.FDW_SHOT_FAILED, fdw.FDW_SHOT_DONE]
+        rec_a, _ = sv.fetch(tk[0])
+        assert rec_a.shape == (5, 0)
+        rec_b, _ = sv.fetch(tk[1])
+        assert rec_b.shape == (1, 40) and not np.any(rec_b)  # no source, zero initial state
+        with pytest.raises(fdw.FdwError) as e:
+            sv.fetch(tk[2])
+        assert e.value.code == fdw.FDW_ERR_STATE and "stab" in str(e.value)
+        rec_d, _ = sv.fetch(tk[3])
+        tr, _ = run_alone(d, torch_dev)
+        np.testing.assert_array_equal(rec_d, tr)
+        for t in tk:
+            sv.release(t)
+    finally:
+        sv.close()
