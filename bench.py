@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps of the bounded CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=400, help="oracle steps of the bounded CPU sample")
     ap.add_argument("--tti", action="store_true", help="also time the 512^3 TTI so=12 operator")
     ap.add_argument("--tti-n", type=int, default=512, help="grid points per axis of the TTI leg (512: the workload)")
     ap.add_argument("--tti-steps", type=int, default=0, help="steps of the TTI leg (0: the workload's 800)")
