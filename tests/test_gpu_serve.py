@@ -196,3 +196,35 @@ def test_server_edge_requests(torch_dev):
             sv.release(t)
     finally:
         sv.close()
+
+
+def test_batch_rejects_what_it_cannot_fuse(torch_dev):
+    """Mismatched geometry or order, scatter-injected sources and adjoint
+    operators are refused before any launch."""
+    from paper_1807_03032_amd import fdw
+    p1 = W.serve_problem("iso", 3, 40, 8, 10, seed=60, nbl=8)
+    p2 = W.serve_problem("iso", 3, 44, 8, 10, seed=61, nbl=8)     # other shape
+    p3 = W.serve_problem("iso", 3, 40, 4, 10, seed=62, nbl=8)     # other order
+    pts = np.random.default_rng(2).uniform(0.2, 0.8, size=(6, 3)) * np.array(p1.extent)
+    p4 = W.small_problem("iso", (40, 40, 40), 8, nt=10, seed=63, src_at=pts, nrec=4, nbl=8)  # 6 sources
+    shots = [fdw.Shot(p, torch_dev, nslots=2) for p in (p1, p2, p3, p4)]
+    b = fdw.fdw_batch_create()
+    try:
+        for other in shots[1:]:
+            with pytest.raises(fdw.FdwError) as e:
+                fdw.fdw_batch_apply(b, [shots[0].op, other.op], [0, 0], [4, 4])
+            assert e.value.code == fdw.FDW_ERR_ARG
+        with pytest.raises(fdw.FdwError) as e:
+            fdw.fdw_batch_apply(b, [shots[0].op], [0], [10])  # beyond the 10 source samples
+        assert e.value.code == fdw.FDW_ERR_ARG
+        fdw.fdw_batch_apply(b, [shots[0].op], [0], [9])
+        torch_sync()
+    finally:
+        fdw.fdw_batch_destroy(b)
+        for s in shots:
+            s.close()
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
