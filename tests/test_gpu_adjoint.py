@@ -143,3 +143,48 @@ def test_autograd_finite_difference(dev):
         assert abs(fd - an) <= 2e-2 * abs(an)
     finally:
         md.close()
+
+
+def test_adjoint_320_full_size_properties(dev):
+    """The 320^3, so = 8, 1500-step gradient workload at full size, checked by
+    properties that hold at any size (the oracle cannot hold 1500 levels of a
+    320^3 grid): the FP32 adjoint dot-product test on the real geometry and the
+    gradient's independence of the checkpoint interval (50 vs 300 steps:
+    recomputed segments repeat the same arithmetic, up to the order of the
+    atomic injection sums)."""
+    import torch
+
+    from paper_1807_03032_amd.modeling import IsoModeling
+    prob, m_true = W.config_3d_iso_adjoint_320()
+    say("adjoint 320^3 full size")
+    md = IsoModeling(prob.shape, prob.extent, prob.origin, prob.so, prob.dt, prob.nt, prob.nbl, prob.vmax,
+                     prob.src_coords, prob.rec_coords, device=dev, checkpoint_every=50, rc=prob.rc)
+    try:
+        md.set_m(m_true)
+        d_obs = md.forward(prob.src, checkpoints=False)
+        md.set_m(prob.fields["m"])
+        resid = md.forward(prob.src, checkpoints=True) - d_obs
+        g50 = md.gradient(resid)
+        ftd = md.adjoint(resid)
+        fq = md.forward(prob.src, checkpoints=False)
+        lhs = float(torch.sum(fq.double() * resid.double()))
+        rhs = float(torch.sum(torch.as_tensor(prob.src, device=dev).double() * ftd.double()))
+        dot = abs(lhs - rhs) / abs(lhs)
+        say("dot", f"{dot:.2e}")
+        assert dot <= 1e-5
+        assert torch.isfinite(g50).all() and float(torch.linalg.norm(g50)) > 0
+    finally:
+        md.close()
+    md = IsoModeling(prob.shape, prob.extent, prob.origin, prob.so, prob.dt, prob.nt, prob.nbl, prob.vmax,
+                     prob.src_coords, prob.rec_coords, device=dev, checkpoint_every=300, rc=prob.rc)
+    try:
+        md.set_m(prob.fields["m"])
+        md.forward(prob.src, checkpoints=True)
+        g300 = md.gradient(resid)
+        # the 102,400 residual points are injected with atomic adds (receivers
+        # share grid corners), so sums may round in another order
+        e = float(torch.linalg.norm((g300 - g50).double()) / torch.linalg.norm(g50.double()))
+        say("checkpoint interval", f"{e:.2e}")
+        assert e <= 1e-5
+    finally:
+        md.close()
