@@ -435,6 +435,19 @@ __global__ void __launch_bounds__(64 * BY) stream3d_multi(const StreamShot<Op, N
                                          S.live != 0);
 }
 
+// z-chunk length for a grid: the longest chunk (up to zc_max) that still gives
+// `full` workgroups -- long chunks re-read fewer warm-up planes, which decides
+// large grids -- else the longest that gives `latency` workgroups, since each
+// workgroup walks its chunk plane by plane and small grids are bound by that
+// serial latency; 4 at least.
+static inline int adaptive_zchunk(int64_t columns, int nz, int zc_max, int64_t full, int64_t latency) {
+    auto wgs = [&](int zc) { return columns * (int64_t)((nz + zc - 1) / zc); };
+    if (wgs(zc_max) >= full) return std::min(zc_max, nz);
+    for (int zc = zc_max / 2; zc >= 4; zc /= 2)
+        if (wgs(zc) >= latency) return std::min(zc, nz);
+    return std::min(4, nz);
+}
+
 // Workgroups that sample receivers inside a streaming launch (each loops over
 // its share; FDW_INTERP_WG overrides the default for tuning).
 static inline int64_t interp_workgroups() {

@@ -228,8 +228,15 @@ struct IsoShape {
     int ny, zc, pf, by;
 };
 
+// default shape 64 x 8 tile, 4 waves, prefetch 2; z-chunk 32 for large grids,
+// shorter when the grid has too few tile columns to occupy the chip
+static int iso_default_zchunk(const Geom &g) {
+    const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
+    return adaptive_zchunk(cols, g.nz, 32, 1024, 2048);
+}
+
 static IsoShape iso_stream_shape(const Geom &g) {
-    IsoShape sh{2, 32, 2, 4};
+    IsoShape sh{2, iso_default_zchunk(g), 2, 4};
     if (const char *e = std::getenv("FDW_ISO_TILE")) {
         int a = 0, b = 0, c = 1, d = 4;
         const int n = std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d);
@@ -338,8 +345,8 @@ template <int R>
 static hipError_t launch_iso_multi_r(int ndim, const Geom &g, const void *recs, int n, int64_t rec_lanes,
                                      hipStream_t s) {
     if (ndim == 3) {
-        const IsoShape sh{2, 32, 2, 4};
-        return launch_stream3d_multi<R, 2, 2, 4>(static_cast<const IsoShot3 *>(recs), n, rec_lanes, g, sh.zc, s);
+        return launch_stream3d_multi<R, 2, 2, 4>(static_cast<const IsoShot3 *>(recs), n, rec_lanes, g,
+                                                 iso_default_zchunk(g), s);
     }
     dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.nz + 3) / 4, n);
     hipLaunchKernelGGL((iso2d_naive_multi<R>), grd, blk, 0, s, static_cast<const NaiveShot<IsoArgs> *>(recs));

@@ -224,8 +224,15 @@ struct TtiShape {
     int ny1, by1, ny2, by2, zc;
 };
 
+// z-chunk of both stages: 64 for large grids, shorter when stage 2's 64 x 8
+// tile columns are too few to occupy the chip
+static int tti_default_zchunk(const Geom &g) {
+    const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
+    return adaptive_zchunk(cols, g.nz, 64, 2048, 2048);
+}
+
 static TtiShape tti_stream_shape(const Geom &g) {
-    TtiShape sh{2, 8, 1, 8, 64};
+    TtiShape sh{2, 8, 1, 8, tti_default_zchunk(g)};
     if (const char *e = std::getenv("FDW_TTI_TILE")) {
         int a = 0, b = 0, c = 0, d = 0, z = 0;
         if (std::sscanf(e, "%d,%d,%d,%d,%d", &a, &b, &c, &d, &z) == 5 && (a == 1 || a == 2) && (b == 4 || b == 8) &&
@@ -341,10 +348,11 @@ static hipError_t launch_tti_multi_r(int ndim, const Geom &g, const void *recs1,
                                      int64_t rec_lanes, hipStream_t s) {
     if (ndim == 3) {
         constexpr int NY1 = 2, BY1 = 8, NY2 = 1, BY2 = 8;
+        const int zc = tti_default_zchunk(g);
         hipError_t e = launch_stream3d_multi<R, NY1, 1, BY1>(static_cast<const TtiShot1 *>(recs1), n, rec_lanes, g,
-                                                             64, s);
+                                                             zc, s);
         if (e != hipSuccess) return e;
-        return launch_stream3d_multi<R, NY2, 1, BY2>(static_cast<const TtiShot2 *>(recs2), n, 0, g, 64, s);
+        return launch_stream3d_multi<R, NY2, 1, BY2>(static_cast<const TtiShot2 *>(recs2), n, 0, g, zc, s);
     }
     const auto *sh = static_cast<const NaiveShot<TtiArgs> *>(recs1);
     dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.nz + 3) / 4, n);
