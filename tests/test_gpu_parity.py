@@ -322,3 +322,15 @@ def test_kernel_timing_covers_every_launch(torch_dev):
         fdw.fdw_operator_set_timing(shot.op, 0)
     finally:
         shot.close()
+
+
+@pytest.mark.parametrize("kind,shape,so", [("iso", (9, 7, 5), 16), ("tti", (11, 9, 6), 16), ("iso", (5, 3), 16),
+                                           ("tti", (6, 5), 12), ("iso", (3, 70, 4), 8), ("iso", (130, 2, 3), 4)])
+def test_grids_smaller_than_the_stencil(torch_dev, kind, shape, so):
+    """Axes shorter than the stencil radius (or than a tile): every neighbour
+    beyond the domain is the zero halo."""
+    prob = W.small_problem(kind, shape, so, nt=12, seed=80, nsrc=1, nrec=3, nbl=1)
+    say("tiny", kind, shape, so)
+    gf, gtr, _ = gpu_run(prob, torch_dev)
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
