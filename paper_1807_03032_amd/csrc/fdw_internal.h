@@ -209,7 +209,7 @@ hipError_t launch_zero_halo(int ndim, const Geom &g, int R, int64_t pitch_x, int
                             int64_t planes, float *base, hipStream_t s);
 
 // Human-readable description of the launch plan of the dominant kernel.
-const char *iso_kernel_name(int ndim, IsoVariant v);
-const char *tti_kernel_name(int ndim, TtiVariant v);
+const char *iso_kernel_name(int ndim, IsoVariant v, const Geom &g);
+const char *tti_kernel_name(int ndim, TtiVariant v, const Geom &g);
 
 }  // namespace fdw

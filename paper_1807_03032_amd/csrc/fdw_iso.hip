@@ -547,11 +547,9 @@ hipError_t launch_iso2d_tb(int R, const TB2DArgs &a, hipStream_t s, const Launch
 #undef TBR
 }
 
-const char *iso_kernel_name(int ndim, IsoVariant v) {
+const char *iso_kernel_name(int ndim, IsoVariant v, const Geom &g) {
     if (ndim == 3 && v == IsoVariant::Stream) {
-        static char buf[96];
-        Geom g{};
-        g.nz = 1 << 30;
+        static thread_local char buf[96];
         const IsoShape sh = iso_stream_shape(g);
         std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x%d (%d waves) zchunk=%d prefetch=%d", sh.by * sh.ny,
                       sh.by, sh.zc, sh.pf);

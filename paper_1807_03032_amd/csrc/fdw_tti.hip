@@ -382,11 +382,9 @@ hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream
 #undef TTI_N3
 #undef TTI_N2
 }
-const char *tti_kernel_name(int ndim, TtiVariant v) {
+const char *tti_kernel_name(int ndim, TtiVariant v, const Geom &g) {
     if (ndim == 3 && v == TtiVariant::Stream) {
-        static char buf[96];
-        Geom g{};
-        g.nz = 1 << 30;
+        static thread_local char buf[96];
         const TtiShape sh = tti_stream_shape(g);
         std::snprintf(buf, sizeof(buf), "tti3d_stream stage1 tile=64x%d stage2 tile=64x%d zchunk=%d", sh.by1 * sh.ny1,
                       sh.by2 * sh.ny2, sh.zc);
