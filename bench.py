@@ -520,7 +520,7 @@ def main():
                        "value": round(pt.npoints * pt.nt / w2 / 1e9, 3), "unit": "GPts/s",
                        "roofline": roofline(pt, k2, l2, b2, load_traffic("tti", d2))}
         ops_seen.append({"desc": d2, "source_hash": source_hash("tti"), "kernel_match": ["TtiS1Op", "TtiS2Op", "tti_naive"]})
-        p2 = parity_vs_stored("3d_tti_512", pt, pt.nt, tr2, f2) if args.tti_n == 512 else None
+        p2 = parity_vs_stored("3d_tti_512", pt, pt.nt, tr2, f2) if (args.tti_n, pt.nt) == (512, 800) else None
         if p2 is not None:
             line["tti"]["parity_rel_l2_sampled"] = p2
     if args.adjoint:
