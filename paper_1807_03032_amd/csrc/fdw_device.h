@@ -171,10 +171,12 @@ __device__ __forceinline__ void interp_lane(const SparseArgs &a, int lane) {
 //   * NP "pointwise" fields, read only at the output point.
 // Loads for plane z + PF (queue heads, pointwise values, halo) are issued
 // before the plane-z arithmetic, so PF planes of loads are in flight.
-// Points outside the domain are never read: the zero Dirichlet halo is written
-// into LDS / the queues directly.  Workgroup ids are remapped so that the
-// workgroups one XCD receives (ids congruent mod 8) cover a contiguous block of
-// tiles and share halo rows and warm-up planes in that XCD's L2.
+// A neighbour outside the domain reads as zero without touching the halo
+// memory (see load_at); addresses are a wave-uniform plane offset plus a
+// loop-invariant 32-bit byte offset per lane.  Workgroup ids are remapped so
+// that the workgroups one XCD receives (ids congruent mod 8) cover a
+// contiguous block of tiles and share halo rows and warm-up planes in that
+// XCD's L2.
 // The operator functor Op computes and stores the outputs of one point from
 // a StreamPoint view of the registers and LDS.
 // ---------------------------------------------------------------------------
@@ -187,8 +189,46 @@ template <int NQ, int NP>
 struct StreamFields {
     const float *q[NQ];  // stencil fields
     const float *p[NP];  // pointwise fields
-    float pout[NP];      // value used outside the domain
 };
+
+// Raw buffer accesses for the streaming engine.  The descriptor holds a
+// wave-uniform base (scalar registers) and a record count; the per-lane
+// offset is a 32-bit byte offset, so no per-lane 64-bit address arithmetic is
+// needed.  The hardware bounds-checks every access against the record count:
+// a load at or past it returns zero and a store there is dropped, which is how
+// the engine reads the zero Dirichlet exterior without branches or memory
+// traffic -- lanes outside the domain carry the offset kBufOut, and a plane
+// outside the domain gets a descriptor with no records.  Valid offsets stay
+// below kBufOut (a plane of the padded layout is below 2 GiB).  Descriptor
+// word 3 is the gfx9-family raw-buffer format.
+constexpr uint32_t kBufOut = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_at(const float *base, bool valid) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, valid ? (int)kBufOut : 0, 0x00020000);
+}
+// Element at byte offset vb within plane zo (element offset of the plane's
+// (0, 0), wave-uniform) of a field; vb = kBufOut or valid = false (a plane
+// outside the domain) read as zero and drop stores.  BUF = true: raw buffer
+// accesses as above, no branches.  BUF = false: global accesses at the
+// field's base (scalar) + a 32-bit byte offset, branching around the lanes
+// and planes outside the domain; the field must be below 4 GiB.  Each operator
+// picks the form that measures faster for it: the TTI stages, with many loads
+// per point and VALU-bound, gain from the buffer form; the isotropic step,
+// bound by HBM bandwidth, runs slightly faster with global accesses.
+template <bool BUF>
+__device__ __forceinline__ float load_at(const float *f, int64_t zo, uint32_t vb, bool valid = true) {
+    if constexpr (BUF)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(buffer_at(f + zo, valid), (int)vb, 0, 0));
+    else
+        return valid && vb != kBufOut ? *(const float *)((const char *)f + ((uint32_t)zo * 4u + vb)) : 0.0f;
+}
+template <bool BUF>
+__device__ __forceinline__ void store_at(float *f, int64_t zo, uint32_t vb, float v) {
+    if constexpr (BUF)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), buffer_at(f + zo, true), (int)vb, 0,
+                                              0);
+    else if (vb != kBufOut)
+        *(float *)((char *)f + ((uint32_t)zo * 4u + vb)) = v;
+}
 
 // Loads of one plane that a thread issues ahead of use (prefetch ring entry).
 template <int NQ, int NP, int NY, int NHY, int NHX>
@@ -201,20 +241,23 @@ struct PlaneLoads {
 };
 
 // What an operator sees for one output point.
-template <int R, int NQ, int NP, int NY, int LH, int LW, int DIR>
+template <int R, int NQ, int NP, int NY, int LH, int LW, int DIR, bool BUF>
 struct StreamPoint {
     const float (&q)[NQ][NY][2 * R + 1];
     const float (&lds)[NQ][LH][LW];
     const float (&pw)[NP][NY];
     int j, ly, lx;        // column index in the thread, LDS coordinates
     int x, y, z;          // grid coordinates
-    uint32_t off;         // element offset of the point
+    int64_t zb;           // element offset of (0, 0) in plane z (uniform)
+    uint32_t vb;          // byte offset of the point from there (kBufOut outside the domain)
     // field f at (x, y, z + k), (x + k, y, z), (x, y + k, z); k in [-R, R]
     // (queue entry R + i holds plane z + DIR * i)
     __device__ __forceinline__ float qz(int f, int k) const { return q[f][j][R + DIR * k]; }
     __device__ __forceinline__ float qx(int f, int k) const { return lds[f][ly][lx + k]; }
     __device__ __forceinline__ float qy(int f, int k) const { return lds[f][ly + k][lx]; }
     __device__ __forceinline__ float p(int i) const { return pw[i][j]; }
+    // stores v at the point's element of an output field in the same layout
+    __device__ __forceinline__ void store(float *f, float v) const { store_at<BUF>(f, zb, vb, v); }
 };
 
 template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
@@ -237,6 +280,7 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
     // neighbour is then a multiple of 256 bytes, which the paired LDS reads
     // encode as an immediate (no per-neighbour address arithmetic)
     constexpr int TX = 64, TY = BY * NY, LW = (TX + 2 * R + 63) / 64 * 64, LH = TY + 2 * R, Q = 2 * R + 1;
+    constexpr bool BUF = Op::kBufferAccess;
     constexpr int NHY = (2 * R + BY - 1) / BY;       // y-halo rows per wavefront
     constexpr int NHX = (TY * 2 * R + NT - 1) / NT;  // x-halo elements per thread
     __shared__ float lds[2][NQ][LH][LW];
@@ -259,49 +303,53 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
     const int z1 = min(z0 + zc, g.nz);
     const int x = x0 + lane;
     const bool xin = x < g.nx;
-    // 32-bit element offsets (a slot holds fewer than 2^31 elements)
-    const uint32_t sy = (uint32_t)g.sy, sz = (uint32_t)g.sz;
+    // plane z's element (0, 0) is at pbase + z * sz; (x, y) is y * sy + x
+    // elements further, or out of bounds (kBufOut) outside the domain
+    const int64_t pbase = g.off0;
+    auto vbyte = [&](int xx, int yy) {
+        return xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny ? (uint32_t)(((int64_t)yy * g.sy + xx) * 4) : kBufOut;
+    };
     const int yb = y0 + wy * NY;  // first y column of this thread
     bool in[NY];
+    uint32_t vcol[NY];
 #pragma unroll
-    for (int j = 0; j < NY; ++j) in[j] = xin && yb + j < g.ny;
-    const uint32_t col0 = (uint32_t)(g.off0 + (int64_t)yb * g.sy + x);
+    for (int j = 0; j < NY; ++j) {
+        in[j] = xin && yb + j < g.ny;
+        vcol[j] = vbyte(x, yb + j);
+    }
     // per-column constants of the operator, computed once
     float colv[NY];
 #pragma unroll
     for (int j = 0; j < NY; ++j) colv[j] = in[j] ? op.begin_column(x, yb + j) : 0.0f;
 
     // y-halo rows handled by this wavefront: hr = wy + BY * i
-    bool hy_in[NHY], hy_act[NHY];
+    bool hy_act[NHY];
     int hy_lds[NHY];
-    uint32_t hy_col[NHY];
+    uint32_t hy_vb[NHY];
 #pragma unroll
     for (int i = 0; i < NHY; ++i) {
         const int hr = wy + BY * i;
         const int yy = hr < R ? y0 - R + hr : y0 + TY + (hr - R);
         hy_act[i] = hr < 2 * R;
         hy_lds[i] = hr < R ? hr : R + TY + (hr - R);
-        hy_in[i] = hy_act[i] && xin && yy >= 0 && yy < g.ny;
-        hy_col[i] = hy_in[i] ? (uint32_t)(g.off0 + (int64_t)yy * g.sy + x) : 0u;
+        hy_vb[i] = hy_act[i] ? vbyte(x, yy) : kBufOut;
     }
     // x-halo elements handled by this thread (TY rows x 2R columns)
-    bool hx_act[NHX], hx_in[NHX];
+    bool hx_act[NHX];
     int hx_lrow[NHX], hx_lcol[NHX];
-    uint32_t hx_off[NHX];
+    uint32_t hx_vb[NHX];
 #pragma unroll
     for (int i = 0; i < NHX; ++i) {
         const int xi = threadIdx.x + NT * i;
         hx_act[i] = xi < TY * 2 * R;
         const int hx_r = xi / (2 * R), hx_c = xi % (2 * R);
         const int hx_x = hx_c < R ? x0 - R + hx_c : x0 + TX + (hx_c - R);
-        hx_in[i] = hx_act[i] && hx_x >= 0 && hx_x < g.nx && y0 + hx_r < g.ny;
         hx_lrow[i] = R + hx_r;
         hx_lcol[i] = hx_c < R ? hx_c : R + TX + (hx_c - R);
-        hx_off[i] = hx_in[i] ? (uint32_t)(g.off0 + (int64_t)(y0 + hx_r) * g.sy + hx_x) : 0u;
+        hx_vb[i] = hx_act[i] ? vbyte(hx_x, y0 + hx_r) : kBufOut;
     }
     const bool tile_flag = op.begin_tile(x0, TX, y0, TY, z0, z1);
 
-    auto zin = [&](int z) { return z >= 0 && z < g.nz; };
     // Chunks alternate their walking direction along z (even chunk index: up,
     // odd: down), so the two chunks that share a boundary read its warm-up
     // planes at the same time -- both at their start or both at their end --
@@ -312,23 +360,23 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
         const int nplanes = z1 - z0;
         const int zs = DIR > 0 ? z0 : z1 - 1;  // first plane walked
         auto issue = [&](PlaneLoads<NQ, NP, NY, NHY, NHX> &P, int z) {
-            const uint32_t zo = (uint32_t)z * sz;
-            const uint32_t zh = (uint32_t)(z + DIR * R) * sz;
-            const bool hin = zin(z + DIR * R);
+            const int64_t zb = pbase + (int64_t)z * g.sz;
+            const int zhp = z + DIR * R;
+            const int64_t zh = pbase + (int64_t)zhp * g.sz;
+            const bool hin = zhp >= 0 && zhp < g.nz;
 #pragma unroll
             for (int f = 0; f < NQ; ++f) {
 #pragma unroll
-                for (int j = 0; j < NY; ++j)
-                    P.head[f][j] = (in[j] && hin) ? F.q[f][col0 + j * sy + zh] : 0.0f;
+                for (int j = 0; j < NY; ++j) P.head[f][j] = load_at<BUF>(F.q[f], zh, vcol[j], hin);
 #pragma unroll
-                for (int i = 0; i < NHY; ++i) P.hy[f][i] = hy_in[i] ? F.q[f][hy_col[i] + zo] : 0.0f;
+                for (int i = 0; i < NHY; ++i) P.hy[f][i] = load_at<BUF>(F.q[f], zb, hy_vb[i]);
 #pragma unroll
-                for (int i = 0; i < NHX; ++i) P.hx[f][i] = hx_in[i] ? F.q[f][hx_off[i] + zo] : 0.0f;
+                for (int i = 0; i < NHX; ++i) P.hx[f][i] = load_at<BUF>(F.q[f], zb, hx_vb[i]);
             }
 #pragma unroll
             for (int f = 0; f < NP; ++f)
 #pragma unroll
-                for (int j = 0; j < NY; ++j) P.pw[f][j] = in[j] ? F.p[f][col0 + j * sy + zo] : F.pout[f];
+                for (int j = 0; j < NY; ++j) P.pw[f][j] = load_at<BUF>(F.p[f], zb, vcol[j]);
             P.pv = op.begin_plane(z);
         };
 
@@ -341,7 +389,7 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
 #pragma unroll
                 for (int k = 0; k < 2 * R; ++k) {
                     const int z = zs + DIR * (k - R);
-                    q[f][j][k] = (in[j] && zin(z)) ? F.q[f][col0 + j * sy + (uint32_t)z * sz] : 0.0f;
+                    q[f][j][k] = load_at<BUF>(F.q[f], pbase + (int64_t)z * g.sz, vcol[j], z >= 0 && z < g.nz);
                 }
         PlaneLoads<NQ, NP, NY, NHY, NHX> P[PF];
 #pragma unroll
@@ -386,8 +434,9 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
                 lds_barrier();
 #pragma unroll
                 for (int j = 0; j < NY; ++j) {
-                    StreamPoint<R, NQ, NP, NY, LH, LW, DIR> pt{q, lds[buf], cpw, j, R + wy * NY + j, R + lane,
-                                                               x, yb + j, z, col0 + j * sy + (uint32_t)z * sz};
+                    StreamPoint<R, NQ, NP, NY, LH, LW, DIR, BUF> pt{q,     lds[buf], cpw,   j,
+                                                               R + wy * NY + j, R + lane, x, yb + j,
+                                                               z,     pbase + (int64_t)z * g.sz, vcol[j]};
                     // computed for every column (keeps the NY columns in one scheduling
                     // region); only stores are predicated on the column being in the domain
                     op.template point<R>(pt, tile_flag, colv[j] + plane_val, in[j]);

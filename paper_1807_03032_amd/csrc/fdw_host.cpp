@@ -533,8 +533,12 @@ static void pick_variants(fdw_op *op) {
     // FDW_KERNEL=naive forces the one-thread-per-point kernels (A/B checks).
     const char *k = std::getenv("FDW_KERNEL");
     const bool naive = k && std::strcmp(k, "naive") == 0;
-    op->iso_v = naive ? IsoVariant::Naive : IsoVariant::Stream;
-    op->tti_v = naive ? TtiVariant::Naive : TtiVariant::Stream;
+    // the streaming kernels address within a plane of the padded layout with
+    // byte offsets below 2^31 (larger offsets read as zero): planes above
+    // 2 GiB take the per-point kernels
+    const bool big_plane = op->lay.pitch_x * op->lay.pitch_y * (int64_t)sizeof(float) > ((int64_t)1 << 31);
+    op->iso_v = naive || big_plane ? IsoVariant::Naive : IsoVariant::Stream;
+    op->tti_v = naive || big_plane ? TtiVariant::Naive : TtiVariant::Stream;
     // the persistent kernel handles linear (2 x 2) sparse supports only
     const bool linear = (!op->d.src || op->d.src->r == 2) && (!op->d.rec || op->d.rec->r == 2);
     op->use_persist2d = !naive && linear && op->d.kind == FDW_ISO && op->ndim == 2 && op->d.mode == FDW_FORWARD &&
@@ -1301,6 +1305,8 @@ int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, 
             return fail(FDW_ERR_ARG, "batch_apply: op %d: forward operators without level saving only", i);
         if (ndim == 3 && (kind == FDW_ISO ? op->iso_v != IsoVariant::Stream : op->tti_v != TtiVariant::Stream))
             return fail(FDW_ERR_ARG, "batch_apply: op %d: 3D operators need the streaming kernels", i);
+        if (ndim == 3 && kind == FDW_ISO && iso_wide_fields(g))
+            return fail(FDW_ERR_ARG, "batch_apply: op %d: fields of 4 GiB or more are applied one shot at a time", i);
         const int nsrc = d.src ? d.src->npoint : 0, nrec = d.rec ? d.rec->npoint : 0;
         if (nsrc > 0 && !op->src_fused)
             return fail(FDW_ERR_ARG, "batch_apply: op %d: at most %d sources with linear weights per shot", i,

@@ -43,6 +43,9 @@ struct Geom {
     int64_t off0;      // element offset of logical (0, 0, 0)
 };
 
+// Does a 3D field of this geometry reach 4 GiB (beyond 32-bit byte offsets)?
+inline bool iso_wide_fields(const Geom &g) { return (g.off0 + (int64_t)g.nz * g.sz) * 4 > (int64_t)UINT32_MAX; }
+
 struct IsoArgs {
     Geom g;
     const float *u_cur, *u_prev, *m;

@@ -47,6 +47,7 @@ __global__ void __launch_bounds__(256) iso2d_naive_multi(const NaiveShot<IsoArgs
 
 // ---- isotropic step: stencil field u(t); pointwise u(t-1), m ----------------
 struct IsoOp {
+    static constexpr bool kBufferAccess = false;  // raw buffer (true) or global accesses
     Coefs c;
     DampTables eta;
     float dt2;
@@ -78,8 +79,8 @@ struct IsoOp {
         float v = leapfrog(uc, pt.p(0), dt2 * rm * lap, a);
         if (src_here) v = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, v, adjoint ? 1.0f / (1.0f + a) : 1.0f);
         if (live) {
-            u_next[pt.off] = v;
-            if (save) save[pt.off] = v;
+            pt.store(u_next, v);
+            if (save) pt.store(save, v);
         }
     }
 };
@@ -248,6 +249,17 @@ static IsoShape iso_stream_shape(const Geom &g) {
 }
 
 static IsoOp make_iso_op(const IsoArgs &a);
+
+// Fields of 4 GiB or more are beyond the global accesses' 32-bit byte
+// offsets: they take the raw buffer form (offsets within one plane).
+struct IsoOpWide : IsoOp {
+    static constexpr bool kBufferAccess = true;
+};
+// (FDW_ISO_WIDE=1 takes the wide form on any grid: checks of that path)
+static bool iso_wide_form(const Geom &g) {
+    const char *e = std::getenv("FDW_ISO_WIDE");
+    return (e && e[0] == '1') || iso_wide_fields(g);
+}
 static StreamFields<1, 2> iso_fields(const IsoArgs &a);
 
 template <int R, int NY, int PF, int BY>
@@ -272,6 +284,10 @@ static hipError_t launch_iso3d_stream_ny(const IsoArgs &a, const IsoShape &sh, h
 template <int R>
 static hipError_t launch_iso3d_stream(const IsoArgs &a, hipStream_t s, const LaunchEvents &ev) {
     const IsoShape sh = iso_stream_shape(a.g);
+    // FDW_ISO_WIDE=1 takes the wide form on any grid (checks of that path)
+    if (iso_wide_form(a.g))
+        return launch_stream3d<R, 2, 2, 4>(IsoOpWide{make_iso_op(a)}, iso_fields(a), a.g, sh.zc, s, ev.start, ev.stop,
+                                           a.rec);
     if constexpr (R == 4) {
         if (sh.ny == 1) return launch_iso3d_stream_ny<R, 1>(a, sh, s, ev);
         if (sh.ny == 2) return launch_iso3d_stream_ny<R, 2>(a, sh, s, ev);
@@ -313,8 +329,6 @@ static StreamFields<1, 2> iso_fields(const IsoArgs &a) {
     F.q[0] = a.u_cur;
     F.p[0] = a.u_prev;
     F.p[1] = a.m;
-    F.pout[0] = 0.0f;
-    F.pout[1] = 1.0f;
     return F;
 }
 
@@ -551,8 +565,11 @@ const char *iso_kernel_name(int ndim, IsoVariant v, const Geom &g) {
     if (ndim == 3 && v == IsoVariant::Stream) {
         static thread_local char buf[96];
         const IsoShape sh = iso_stream_shape(g);
-        std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x%d (%d waves) zchunk=%d prefetch=%d", sh.by * sh.ny,
-                      sh.by, sh.zc, sh.pf);
+        if (iso_wide_form(g))
+            std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x8 (4 waves) zchunk=%d prefetch=2 wide", sh.zc);
+        else
+            std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x%d (%d waves) zchunk=%d prefetch=%d", sh.by * sh.ny,
+                          sh.by, sh.zc, sh.pf);
         return buf;
     }
     return ndim == 3 ? "iso_naive<3>" : "iso_naive<2>";

@@ -122,6 +122,7 @@ __device__ __forceinline__ void tti_normal3(float th, float ph, float &nx, float
 // ---- TTI stage 1: stencil fields p, r; pointwise theta, phi ------------------
 //   gp = n . grad p,  gr = n . grad r   (order-2R centred first derivatives)
 struct TtiS1Op {
+    static constexpr bool kBufferAccess = true;  // raw buffer (true) or global accesses
     Coefs c;
     float *gp, *gr;
     __device__ __forceinline__ bool begin_tile(int, int, int, int, int, int) const { return false; }
@@ -141,7 +142,7 @@ struct TtiS1Op {
                 dz += c.w1[2][k] * (pt.qz(f, k) - pt.qz(f, -k));
             }
             const float gv = nx * dx + ny * dy + nz * dz;
-            if (live) (f == 0 ? gp : gr)[pt.off] = gv;
+            if (live) pt.store(f == 0 ? gp : gr, gv);
         }
     }
 };
@@ -151,6 +152,7 @@ struct TtiS1Op {
 //   Hp = n . grad gp, Hr = n . grad gr, A = L p - Hp, B = Hr
 //   p+ from (1 + 2 eps) A + sqrt(1 + 2 delta) B, r+ from sqrt(1 + 2 delta) A + B
 struct TtiS2Op {
+    static constexpr bool kBufferAccess = true;  // raw buffer (true) or global accesses
     Coefs c;
     DampTables eta;
     float dt2;
@@ -198,8 +200,8 @@ struct TtiS2Op {
             rn = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, rn);
         }
         if (live) {
-            p_next[pt.off] = pn;
-            r_next[pt.off] = rn;
+            pt.store(p_next, pn);
+            pt.store(r_next, rn);
         }
     }
 };
@@ -275,7 +277,6 @@ static void tti_stage1_parts(const TtiArgs &a, TtiS1Op &o1, StreamFields<2, 2> &
     F1.q[1] = a.r_cur;
     F1.p[0] = a.theta;
     F1.p[1] = a.phi;
-    F1.pout[0] = F1.pout[1] = 0.0f;
 }
 
 static void tti_stage2_parts(const TtiArgs &a, TtiS2Op &o2, StreamFields<3, 8> &F2) {
@@ -289,11 +290,7 @@ static void tti_stage2_parts(const TtiArgs &a, TtiS2Op &o2, StreamFields<3, 8> &
     F2.q[1] = a.gr;
     F2.q[2] = a.p_cur;
     const float *pw[8] = {a.p_prev, a.r_cur, a.r_prev, a.m, a.eps, a.delta, a.theta, a.phi};
-    for (int i = 0; i < 8; ++i) {
-        F2.p[i] = pw[i];
-        F2.pout[i] = 0.0f;
-    }
-    F2.pout[3] = 1.0f;  // m
+    for (int i = 0; i < 8; ++i) F2.p[i] = pw[i];
 }
 
 template <int R>

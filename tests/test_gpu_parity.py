@@ -334,3 +334,49 @@ def test_grids_smaller_than_the_stencil(torch_dev, kind, shape, so):
     gf, gtr, _ = gpu_run(prob, torch_dev)
     of, otr = oracle_run(prob)
     check(prob, gf, gtr, of, otr)
+
+
+@pytest.mark.parametrize("shape,so", [((37, 29, 23), 8), ((70, 45, 33), 16), ((9, 7, 5), 4)])
+def test_wide_field_form(torch_dev, monkeypatch, shape, so):
+    """The raw-buffer form of the isotropic step, taken for fields of 4 GiB or
+    more (forced here with FDW_ISO_WIDE=1): the oracle's results, and the same
+    bits as the global-access form."""
+    prob = W.small_problem("iso", shape, so, nt=25, seed=90, nsrc=2, nrec=12)
+    say("wide form", shape, so)
+    gf, gtr, desc = gpu_run(prob, torch_dev, nslots=2)
+    assert "wide" not in desc
+    monkeypatch.setenv("FDW_ISO_WIDE", "1")
+    wf, wtr, wdesc = gpu_run(prob, torch_dev, nslots=2)
+    assert "wide" in wdesc, wdesc
+    of, otr = oracle_run(prob)
+    check(prob, wf, wtr, of, otr)
+    for nm in gf:
+        np.testing.assert_array_equal(wf[nm][1], gf[nm][1])
+        np.testing.assert_array_equal(wf[nm][0], gf[nm][0])
+    np.testing.assert_array_equal(wtr, gtr)
+
+
+@pytest.mark.parametrize("kind,shape,so", [("iso", (37, 29, 23), 8), ("tti", (33, 27, 21), 12), ("iso", (67, 45), 4),
+                                           ("tti", (48, 39), 8), ("iso", (70, 41, 9), 16)])
+def test_parameter_halos_are_not_read(torch_dev, kind, shape, so):
+    """Only the domain points of a Function are read: NaN in the halo and
+    padding of every parameter field changes no bit of the results."""
+    from paper_1807_03032_amd import fdw
+    prob = W.small_problem(kind, shape, so, nt=20, seed=91, nsrc=2, nrec=10)
+    say("parameter halos", kind, shape, so)
+    rf, rtr, _ = gpu_run(prob, torch_dev, nslots=2)
+    shot = fdw.Shot(prob, torch_dev, nslots=2)
+    try:
+        for nm, arr in prob.fields.items():
+            t = shot.par[nm]
+            t.fill_(float("nan"))
+            fdw.upload(t, shot.lay, 0, arr)
+        shot.apply(0, prob.nt - 1)
+        f = shot.fields(prob.nt - 1)
+        tr = shot.traces()
+    finally:
+        shot.close()
+    for nm in rf:
+        np.testing.assert_array_equal(f[nm][1], rf[nm][1])
+        np.testing.assert_array_equal(f[nm][0], rf[nm][0])
+    np.testing.assert_array_equal(tr, rtr)
