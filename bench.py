@@ -49,6 +49,8 @@ def parse():
                          "p50/p99 latency and aggregate GPts/s against sequential per-shot solves")
     ap.add_argument("--serve-count", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=3.0, help="mean request arrivals per second")
+    ap.add_argument("--serve-streams", type=int, default=4, help="server streams (buckets advance concurrently)")
+    ap.add_argument("--serve-chunk-us", type=float, default=20000, help="server chunk length target (us)")
     ap.add_argument("--tb2d", action="store_true",
                     help="also time the 2D temporal blocking (steps per launch on LDS patches) against one "
                          "launch per step on a 2D 8001^2 so=8 grid")
@@ -188,7 +190,7 @@ def run_server(reqs, arrivals, chunk_us=20000, nstreams=4):
         sv.close()
 
 
-def serve_leg(device, count, rate, seed=7):
+def serve_leg(device, count, rate, seed=7, nstreams=4, chunk_us=20000):
     """Served shot stream: Poisson arrivals (rate per second) of requests with
     grids from 2D 201^2 to 3D 400^3, orders 4-16, 500-2000 steps, iso or TTI;
     then the same requests as one burst, and as sequential per-shot solves."""
@@ -207,8 +209,8 @@ def serve_leg(device, count, rate, seed=7):
     # warm-up: one small request of each kind through the server (kernel loading)
     run_server([W.serve_problem(k, nd, n, 8, 20, seed=1) for k in ("iso", "tti") for nd, n in ((2, 201), (3, 48))],
                [0.0] * 4)
-    lat, span, st = run_server(reqs, arrivals)
-    lat_b, span_b, st_b = run_server(reqs, [0.0] * len(reqs))
+    lat, span, st = run_server(reqs, arrivals, chunk_us=chunk_us, nstreams=nstreams)
+    lat_b, span_b, st_b = run_server(reqs, [0.0] * len(reqs), chunk_us=chunk_us, nstreams=nstreams)
     # sequential plain per-shot solves (set-up, all steps, traces), back to back
     torch.cuda.synchronize(device)
     t0 = time.perf_counter()
@@ -240,6 +242,7 @@ def serve_leg(device, count, rate, seed=7):
         "burst_host_admit_s": round(st_b["admit_seconds"], 3), "burst_makespan_s": round(span_b, 3),
         "sequential_s": round(seq, 3),
         "model_generation_s": round(t_gen, 1),
+        "server_streams": nstreams, "chunk_target_us": chunk_us,
     }
 
 
@@ -530,7 +533,8 @@ def main():
     if args.tb2d:
         line["tb2d"] = tb2d_leg(dev)
     if args.serve:
-        line["serve"] = serve_leg(dev, args.serve_count, args.serve_rate)
+        line["serve"] = serve_leg(dev, args.serve_count, args.serve_rate, nstreams=args.serve_streams,
+                                  chunk_us=args.serve_chunk_us)
         line["serve_fused_burst"] = fused_burst_leg(dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)

@@ -145,16 +145,19 @@ __device__ __forceinline__ float corner_damp(const SparseArgs &a, int p, int c) 
 __device__ __forceinline__ void interp_lane(const SparseArgs &a, int lane) {
     const int p = lane / a.ncorner;
     const int c = lane % a.ncorner;
+    // global address space named: the arguments may come from a record in memory
+    using gf = __attribute__((address_space(1))) const float;
+    using gi = __attribute__((address_space(1))) const int64_t;
     float v = 0.0f;
     if (p < a.npoint) {
-        v = a.w[(int64_t)p * a.ncorner + c] * a.field[a.base[p] + corner_offset(a, c)];
+        v = ((gf *)a.w)[(int64_t)p * a.ncorner + c] * ((gf *)a.field)[((gi *)a.base)[p] + corner_offset(a, c)];
         if (a.damp_mode == 2) v *= 1.0f + corner_damp(a, p, c);
     }
     // groups of 4 or 8 lanes are aligned inside the 64-wide wavefront
     v += __shfl_xor(v, 1);
     v += __shfl_xor(v, 2);
     if (a.ncorner == 8) v += __shfl_xor(v, 4);
-    if (p < a.npoint && c == 0) a.rec_row[p] = v;
+    if (p < a.npoint && c == 0) ((__attribute__((address_space(1))) float *)a.rec_row)[p] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -214,12 +217,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_at(const float *base, b
 // picks the form that measures faster for it: the TTI stages, with many loads
 // per point and VALU-bound, gain from the buffer form; the isotropic step,
 // bound by HBM bandwidth, runs slightly faster with global accesses.
+// (Global accesses name the global address space: field pointers read from a
+// record in memory, as in the multi-shot kernels, would otherwise be generic
+// and compile to flat accesses, which also count against the LDS wait
+// counter and so stall every LDS wait behind the loads in flight.)
+using gfloat = __attribute__((address_space(1))) float;
 template <bool BUF>
 __device__ __forceinline__ float load_at(const float *f, int64_t zo, uint32_t vb, bool valid = true) {
     if constexpr (BUF)
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(buffer_at(f + zo, valid), (int)vb, 0, 0));
     else
-        return valid && vb != kBufOut ? *(const float *)((const char *)f + ((uint32_t)zo * 4u + vb)) : 0.0f;
+        return valid && vb != kBufOut ? *(const gfloat *)((const char *)f + ((uint32_t)zo * 4u + vb)) : 0.0f;
 }
 template <bool BUF>
 __device__ __forceinline__ void store_at(float *f, int64_t zo, uint32_t vb, float v) {
@@ -227,7 +235,7 @@ __device__ __forceinline__ void store_at(float *f, int64_t zo, uint32_t vb, floa
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), buffer_at(f + zo, true), (int)vb, 0,
                                               0);
     else if (vb != kBufOut)
-        *(float *)((char *)f + ((uint32_t)zo * 4u + vb)) = v;
+        *(gfloat *)((char *)f + ((uint32_t)zo * 4u + vb)) = v;
 }
 
 // Loads of one plane that a thread issues ahead of use (prefetch ring entry).
@@ -480,7 +488,10 @@ template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
 __global__ void __launch_bounds__(64 * BY) stream3d_multi(const StreamShot<Op, NQ, NP> *__restrict__ shots, Geom g,
                                                          int zc, int ntx, int nty, int zfast, int nb_stencil) {
     const StreamShot<Op, NQ, NP> &S = shots[blockIdx.y];
-    stream3d_body<R, NY, PF, NQ, NP, BY>(S.op, S.F, g, zc, ntx, nty, zfast, S.rec, nb_stencil, (int)blockIdx.x,
+    // the field pointers, read once into registers (the operator and the
+    // receiver arguments stay in the record)
+    const StreamFields<NQ, NP> F = S.F;
+    stream3d_body<R, NY, PF, NQ, NP, BY>(S.op, F, g, zc, ntx, nty, zfast, S.rec, nb_stencil, (int)blockIdx.x,
                                          S.live != 0);
 }
 
@@ -537,6 +548,12 @@ __device__ __forceinline__ bool src_in_tile(const FusedSrc &src, int x0, int tx,
 struct DampTables {
     const float *ex, *ey, *ez;
     __device__ __forceinline__ float at(int x, int y, int z) const { return ex[x] + ey[y] + ez[z]; }
+    // a_x + a_y of a column and a_z of a plane (global address space named:
+    // the tables may be read through a record in memory)
+    __device__ __forceinline__ float column(int x, int y) const {
+        return ((const gfloat *)ex)[x] + ((const gfloat *)ey)[y];
+    }
+    __device__ __forceinline__ float plane(int z) const { return ((const gfloat *)ez)[z]; }
 };
 
 template <int R, int NY, int PF, int BY, int NQ, int NP, class Op>

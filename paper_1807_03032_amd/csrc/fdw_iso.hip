@@ -60,8 +60,8 @@ struct IsoOp {
         return src_in_tile(src, x0, tx, y0, ty, z0, z1);
     }
     // damping: eta_x + eta_y per column, + eta_z per plane
-    __device__ __forceinline__ float begin_column(int x, int y) const { return eta.ex[x] + eta.ey[y]; }
-    __device__ __forceinline__ float begin_plane(int z) const { return eta.ez[z]; }
+    __device__ __forceinline__ float begin_column(int x, int y) const { return eta.column(x, y); }
+    __device__ __forceinline__ float begin_plane(int z) const { return eta.plane(z); }
     template <int R, class P>
     __device__ __forceinline__ void point(const P &pt, bool src_here, float a, bool live) const {
         const float uc = pt.qz(0, 0);

@@ -161,8 +161,8 @@ struct TtiS2Op {
     __device__ __forceinline__ bool begin_tile(int x0, int tx, int y0, int ty, int z0, int z1) const {
         return src_in_tile(src, x0, tx, y0, ty, z0, z1);
     }
-    __device__ __forceinline__ float begin_column(int x, int y) const { return eta.ex[x] + eta.ey[y]; }
-    __device__ __forceinline__ float begin_plane(int z) const { return eta.ez[z]; }
+    __device__ __forceinline__ float begin_column(int x, int y) const { return eta.column(x, y); }
+    __device__ __forceinline__ float begin_plane(int z) const { return eta.plane(z); }
     template <int R, class P>
     __device__ __forceinline__ void point(const P &pt, bool src_here, float a, bool live) const {
         float nx, ny, nz;
