@@ -380,3 +380,48 @@ def test_parameter_halos_are_not_read(torch_dev, kind, shape, so):
         np.testing.assert_array_equal(f[nm][1], rf[nm][1])
         np.testing.assert_array_equal(f[nm][0], rf[nm][0])
     np.testing.assert_array_equal(tr, rtr)
+
+
+def test_tti_parameters_read_at_each_apply(torch_dev):
+    """The 3D TTI kernels use per-point values derived from the parameters at
+    the start of every apply: parameters rewritten after the operator was
+    created are honoured by fdw_operator_apply and by fdw_batch_apply."""
+    import dataclasses
+
+    import torch
+
+    from paper_1807_03032_amd import fdw
+    p1 = W.small_problem("tti", (33, 27, 21), 12, nt=20, seed=92, nsrc=1, nrec=8)
+    f2 = dict(p1.fields)
+    f2["theta"] = 0.5 * p1.fields["theta"]
+    f2["phi"] = p1.fields["phi"] + 0.3
+    f2["m"] = 1.1 * p1.fields["m"]
+    f2["eps"] = 0.5 * p1.fields["eps"]
+    f2["delta"] = 0.5 * p1.fields["delta"]
+    p2 = dataclasses.replace(p1, fields=f2)
+    say("tti parameters at apply")
+    rf, rtr, _ = gpu_run(p2, torch_dev, nslots=2)
+    of, otr = oracle_run(p2)
+    check(p2, rf, rtr, of, otr)
+    for batched in (False, True):
+        shot = fdw.Shot(p1, torch_dev, nslots=2)
+        b = fdw.fdw_batch_create() if batched else None
+        try:
+            for nm, arr in p2.fields.items():
+                fdw.upload(shot.par[nm], shot.lay, 0, arr)
+            if batched:
+                s = torch.cuda.current_stream(torch_dev)
+                fdw.fdw_batch_apply(b, [shot.op], [0], [p1.nt - 1], s.cuda_stream)
+                s.synchronize()
+            else:
+                shot.apply(0, p1.nt - 1)
+            f = shot.fields(p1.nt - 1)
+            tr = shot.traces()
+        finally:
+            if b is not None:
+                fdw.fdw_batch_destroy(b)
+            shot.close()
+        for nm in rf:
+            np.testing.assert_array_equal(f[nm][1], rf[nm][1])
+            np.testing.assert_array_equal(f[nm][0], rf[nm][0])
+        np.testing.assert_array_equal(tr, rtr)
