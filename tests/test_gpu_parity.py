@@ -425,3 +425,53 @@ def test_tti_parameters_read_at_each_apply(torch_dev):
             np.testing.assert_array_equal(f[nm][1], rf[nm][1])
             np.testing.assert_array_equal(f[nm][0], rf[nm][0])
         np.testing.assert_array_equal(tr, rtr)
+
+
+def test_wide_fields_at_real_size(torch_dev):
+    """A grid whose padded fields pass 4 GiB (1056 x 1040 x 1040, so = 8:
+    4.9 GB per field) takes the raw-buffer form of the isotropic step.  With a
+    constant model, a source on a node in the middle and no damping layer, 10
+    steps reach 40 points from the source, so the block around it must equal,
+    bit for bit, the same block of a 101^3 run around the same source (whose
+    boundary lies beyond the reach), and match the oracle's 101^3 run."""
+    import torch
+
+    from paper_1807_03032_amd import fdw
+    h, so, nt, v = 10.0, 8, 10, 2000.0
+    dt = W.cfl_dt(h, v, 3)
+    src = W.f32(W.ricker(15.0, 1.0 / 15.0, dt, nt)).reshape(nt, 1)
+    offs = np.array([[0.0, 0.0, 0.0], [103.7, 51.2, -77.5], [-250.0, 120.0, 30.3], [12.5, -310.0, 205.0]])
+
+    def problem(shape, centre):
+        c = np.array(centre, dtype=np.float64) * h
+        m = np.full(tuple(reversed(shape)), 1.0 / v ** 2, dtype=np.float32)
+        return W.Problem(f"wide_{shape[0]}", "iso", shape, tuple(h * (k - 1) for k in shape), (0.0,) * 3, so, 0, nt,
+                         dt, v, 0.0, {"m": m}, c.reshape(1, 3), src, c + offs)
+
+    small = problem((101, 101, 101), (50, 50, 50))
+    big = problem((1056, 1040, 1040), (528, 520, 520))
+    g = fdw.fdw_grid_create(big.shape, big.extent)
+    lay = fdw.fdw_field_layout(g, so)
+    fdw.fdw_grid_destroy(g)
+    assert lay.elems_per_slot * 4 > 2 ** 32
+    say("wide fields at real size", big.shape, lay.elems_per_slot * 4 / 2 ** 30, "GiB per field")
+    sf, str_, sdesc = gpu_run(small, torch_dev, nslots=2)
+    assert "wide" not in sdesc
+    shot = fdw.Shot(big, torch_dev, nslots=2)
+    try:
+        assert "wide" in fdw.fdw_operator_describe(shot.op)[0]
+        shot.apply(0, nt - 1)
+        torch.cuda.synchronize(torch_dev)
+        blocks = []
+        for lv in (nt - 1, nt):
+            full = fdw.slot_view(shot.wave["u"], shot.lay, lv % 2)
+            blocks.append(full[520 - 50:520 + 51, 520 - 50:520 + 51, 528 - 50:528 + 51].to("cpu").numpy()
+                          .astype(np.float64))
+        btr = shot.traces()
+    finally:
+        shot.close()
+    np.testing.assert_array_equal(blocks[0], sf["u"][0])
+    np.testing.assert_array_equal(blocks[1], sf["u"][1])
+    np.testing.assert_array_equal(btr, str_)
+    of, otr = oracle_run(small)
+    check(small, {"u": tuple(blocks)}, btr, of, otr)
