@@ -245,10 +245,15 @@ static TtiShape tti_stream_shape(const Geom &g) {
     return sh;
 }
 
+// Planes of loads in flight: two for stage 1 (two stencil fields) in its
+// default 64 x 16 shape at space order 12 (2.42 -> 2.38 ms per 512^3 step),
+// one elsewhere (stage 2 with two: 2.95 ms, its registers drop occupancy).
+constexpr int tti_prefetch(int R, int NQ, int NY, int BY) { return R == 6 && NQ == 2 && NY == 2 && BY == 8 ? 2 : 1; }
+
 template <int R, int NY, int BY, class Op, int NQ, int NP>
 static hipError_t launch_tti_stage(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc, hipStream_t s,
                                    hipEvent_t e0, hipEvent_t e1, const SparseArgs *sp) {
-    return launch_stream3d<R, NY, 1, BY>(op, F, g, zc, s, e0, e1, sp);
+    return launch_stream3d<R, NY, tti_prefetch(R, NQ, NY, BY), BY>(op, F, g, zc, s, e0, e1, sp);
 }
 
 // Tuning variants are instantiated for R = 6 (space order 12) only; other
@@ -346,8 +351,8 @@ static hipError_t launch_tti_multi_r(int ndim, const Geom &g, const void *recs1,
     if (ndim == 3) {
         constexpr int NY1 = 2, BY1 = 8, NY2 = 1, BY2 = 8;
         const int zc = tti_default_zchunk(g);
-        hipError_t e = launch_stream3d_multi<R, NY1, 1, BY1>(static_cast<const TtiShot1 *>(recs1), n, rec_lanes, g,
-                                                             zc, s);
+        hipError_t e = launch_stream3d_multi<R, NY1, tti_prefetch(R, 2, NY1, BY1), BY1>(
+            static_cast<const TtiShot1 *>(recs1), n, rec_lanes, g, zc, s);
         if (e != hipSuccess) return e;
         return launch_stream3d_multi<R, NY2, 1, BY2>(static_cast<const TtiShot2 *>(recs2), n, 0, g, zc, s);
     }
