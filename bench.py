@@ -474,7 +474,7 @@ def main():
             json.dump(db, open(TRAFFIC_JSON, "w"), indent=1, sort_keys=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the operators run on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
     import torch
 

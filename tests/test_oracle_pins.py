@@ -428,8 +428,8 @@ def test_tti_plane_wave_periodic(ndim, so):
 
 # ------------------------------------------------- damping, split runs
 def test_damping_profile_shape():
-    """Zero in the interior, symmetric, maximal at the outer faces (reading of
-    the paper's absorbing mask; profile itself is this build's choice)."""
+    """Zero in the interior, symmetric, maximal at the outer faces (the paper
+    names an absorbing mask but not its profile: the quadratic one is a reading)."""
     g = oracle.Grid((30, 20), (290.0, 190.0), so=4, dt=1e-3, nbl=6, vmax=2000.0)
     eta = oracle.damping(g)
     assert eta[10, 15] == 0.0
