@@ -161,6 +161,33 @@ def test_fourier_mode_exact(ndim, so):
     np.testing.assert_allclose(up, math.cos((nt - 1) * th) * phi, atol=1e-10)
 
 
+# ----------------------------------------- convergence to the wave equation
+@pytest.mark.parametrize("so", [8, 16])
+def test_standing_wave_converges_second_order(so):
+    """The leapfrog march converges to the continuous standing wave
+    u = cos(w t) sin(x) cos(2z), w = v sqrt(5), of u_tt = v^2 (u_xx + u_zz):
+    with dt proportional to h (exact initial history) the error at a fixed
+    time falls as dt^2 -- the time discretisation's order, the spatial error
+    h^so being far smaller at these orders (at so = 4 the two are of the same
+    size here and of opposite sign, which hides the order)."""
+    v, T = 1.0, math.pi
+    errs = []
+    for n, nt in ((24, 60), (48, 120)):
+        L = 2 * math.pi
+        h = L / n
+        dt = T / nt  # = 0.2 h
+        g = oracle.Grid((n, n), (L * (n - 1) / n, L * (n - 1) / n), so=so, dt=dt, periodic=True)
+        x = np.arange(n) * h
+        X, Z = np.meshgrid(x, x, indexing="xy")  # numpy order (z, x)
+        phi = np.sin(X) * np.cos(2 * Z)
+        w = v * math.sqrt(5.0)
+        m = np.full(phi.shape, 1 / v ** 2)
+        _, uc, _ = oracle.iso_run(g, m, nt, u_prev=math.cos(w * dt) * phi, u_cur=phi)
+        errs.append(np.abs(uc - math.cos(w * T) * phi).max())
+    rate = math.log2(errs[0] / errs[1])
+    assert errs[1] < 1e-2 and abs(rate - 2.0) < 0.3, (errs, rate)
+
+
 # ------------------------------------------------------------- energy checks
 def _energy(m, un1, un, dt, Lun):
     return float(np.sum(m * ((un1 - un) / dt) ** 2) - np.sum(un1 * Lun))
