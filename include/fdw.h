@@ -267,12 +267,15 @@ int fdw_batch_destroy(fdw_batch *b);
  * non-blocking scheduling round: it retires shots whose work has completed
  * (receiver traces already copied to host memory), admits queued requests in
  * arrival order while their device footprint fits in the budget left (later
- * requests may pass one that does not fit), and enqueues the next chunk of
- * steps of every bucket of running shots -- shots of one kind, grid and space
- * order -- as fused multi-shot launches (fdw_batch_apply, replayed hipGraphs),
- * each bucket on one of nstreams streams so that buckets overlap on the
- * device.  Shots join and leave their bucket between chunks; chunk length
- * aims at chunk_target_us of device time (0: 20 ms).
+ * requests may pass one that does not fit; a few milliseconds of admissions
+ * per call, the rest in later calls), and enqueues the next chunk of steps of
+ * every bucket of running shots -- shots of one kind, grid and space order --
+ * as fused multi-shot launches (fdw_batch_apply, replayed hipGraphs).  Buckets
+ * of shots that fill the GPU alone (4 Mi grid points or more) advance one at a
+ * time, oldest first, on the first stream; the others share the remaining
+ * nstreams - 1 streams and overlap with them on the device (nstreams = 1: one
+ * stream for all).  Shots join and leave their bucket between chunks; chunk
+ * length aims at chunk_target_us of device time (0: 20 ms).
  * Ownership: the host arrays a description points to are borrowed until the
  * shot is admitted (fdw_server_info state RUNNING or DONE); the server owns
  * all device memory (wavefields in two-slot in-place storage).  budget_bytes

@@ -56,6 +56,13 @@ int lib_fail(int st, const char *where) { return sfail(st, "%s: %s", where, fdw_
 
 struct Shot;
 
+// A shot of at least this many grid points fills the chip alone (a 200^3
+// step already gives thousands of workgroups).
+constexpr int64_t kLargePoints = (int64_t)1 << 22;
+
+// Host time one progress call may spend admitting requests.
+constexpr double kAdmitSliceSeconds = 0.004;
+
 // One chunk of a bucket in flight: its completion event and the shots whose
 // last step it contains.
 struct Chunk {
@@ -66,6 +73,7 @@ struct Chunk {
 
 struct Bucket {
     std::string key;
+    bool large = false;  // one shot fills the chip (see kLargePoints)
     hipStream_t stream = nullptr;
     fdw_batch *batch[2] = {nullptr, nullptr};
     int next_batch = 0;
@@ -109,6 +117,7 @@ struct fdw_server {
     std::vector<hipStream_t> streams;
     hipStream_t upload = nullptr;  // model uploads of admissions
     int next_stream = 0;
+    std::vector<Bucket *> large_order;  // large buckets in creation order
     int64_t next_ticket = 1;
     std::deque<Shot *> queue;
     std::map<int64_t, std::unique_ptr<Shot>> shots;
@@ -272,18 +281,24 @@ int admit(fdw_server *sv, Shot *s) {
     if (bit == sv->buckets.end()) {
         auto nb = std::make_unique<Bucket>();
         nb->key = key;
-        nb->stream = sv->streams[sv->next_stream++ % sv->nstreams];
+        int64_t npts = 1;
+        for (int a = 0; a < d.ndim; ++a) npts *= d.shape[a];
+        // Shots that fill the chip alone gain nothing from running beside each
+        // other (they only compete for the caches): large buckets advance one at
+        // a time, in creation order, on stream 0; small ones share the other
+        // streams and fill the gaps.
+        nb->large = npts >= kLargePoints && sv->nstreams > 1;
+        nb->stream = nb->large ? sv->streams[0] : sv->streams[sv->nstreams > 1 ? 1 + sv->next_stream++ % (sv->nstreams - 1) : 0];
         for (auto &bt : nb->batch) {
             st = fdw_batch_create(&bt);
             if (st) return lib_fail(st, "server: batch");
         }
         // chunk length: about chunk_target_us of device time for one shot
-        int64_t npts = 1;
-        for (int a = 0; a < d.ndim; ++a) npts *= d.shape[a];
         const double pts_per_us = d.kind == FDW_TTI ? 40e3 : 250e3;
         const double step_us = (double)npts / pts_per_us + 4.0;
         nb->chunk_steps = (int)std::min(1000.0, std::max(8.0, sv->chunk_target_us / step_us));
         b = nb.get();
+        if (b->large) sv->large_order.push_back(b);
         sv->buckets.emplace(key, std::move(nb));
     } else {
         b = bit->second.get();
@@ -552,8 +567,13 @@ int fdw_server_progress(fdw_server *sv, int *queued, int *running) {
             b->inflight.pop_front();
         }
     }
-    // 2. admissions, in arrival order; requests that do not fit wait
+    // 2. admissions, in arrival order; requests that do not fit wait.  At most
+    // a few milliseconds of host work per call: the chunks of what is already
+    // admitted are launched below, so the GPU starts on the first requests of
+    // a burst while the later ones are still being uploaded.
+    const double t_adm = sv->now();
     for (auto it = sv->queue.begin(); it != sv->queue.end();) {
+        if (sv->now() - t_adm > kAdmitSliceSeconds) break;
         Shot *s = *it;
         if (sv->used + s->footprint > sv->budget) {
             ++it;
@@ -582,11 +602,18 @@ int fdw_server_progress(fdw_server *sv, int *queued, int *running) {
         }
         it = sv->queue.erase(it);
     }
-    // 3. next chunk of every bucket with running shots (two chunks in flight)
+    // 3. next chunk of every bucket with running shots (two chunks in flight);
+    // of the large buckets only the oldest one with running shots
+    Bucket *large_now = nullptr;
+    for (Bucket *b : sv->large_order)
+        if (!b->active.empty()) {
+            large_now = b;
+            break;
+        }
     int nrun = 0;
     for (auto &kv : sv->buckets) {
         Bucket *b = kv.second.get();
-        if (!b->active.empty() && b->inflight.size() < 2) {
+        if (!b->active.empty() && b->inflight.size() < 2 && (!b->large || b == large_now)) {
             const double tl = sv->now();
             int st = launch_chunk(sv, b);
             sv->launch_s += sv->now() - tl;
