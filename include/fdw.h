@@ -249,7 +249,9 @@ int fdw_operator_destroy(fdw_op *op);
  * the streaming kernels.  A batch object owns pinned and device buffers for
  * the per-shot records of one call; on a stream other than the null stream
  * the call's launch sequence is captured in a hipGraph, kept, and replayed by
- * later calls with the same shot count, step count and receiver width.
+ * later calls with the same shot count, step count and receiver width.  A
+ * call with a single 3D shot runs it through fdw_operator_apply (same bits;
+ * no graph and no record upload).
  * Calls on one batch object are ordered on their stream; the object may be
  * reused immediately (the record upload of the previous call is awaited).
  * Errors: FDW_ERR_ARG (mismatch, restriction, range), FDW_ERR_NOMEM,

@@ -44,6 +44,7 @@ def test_batch_equals_single(torch_dev, kind, ndim, n, so):
     try:
         t = [0] * len(probs)
         calls = 0
+        graph_calls = 0  # a lone 3D shot runs the single-shot kernels, without a graph
         while any(t[i] < p.nt for i, p in enumerate(probs)):
             # shots leave the batch when done: the shot count (and graph) changes
             idx = [i for i, p in enumerate(probs) if t[i] < p.nt]
@@ -53,10 +54,12 @@ def test_batch_equals_single(torch_dev, kind, ndim, n, so):
             for i, hi in zip(idx, tM):
                 t[i] = hi + 1
             calls += 1
+            graph_calls += 0 if (ndim == 3 and len(idx) == 1) else 1
         side.synchronize()
         builds = sum(fdw.fdw_batch_stats(b)[0] for b in batches)
         launches = sum(fdw.fdw_batch_stats(b)[1] for b in batches)
-        assert launches == calls and 1 <= builds < calls
+        assert graph_calls < calls if ndim == 3 else graph_calls == calls
+        assert launches == graph_calls and 1 <= builds < graph_calls
         for i, p in enumerate(probs):
             f = shots[i].fields(p.nt - 1)
             tr = shots[i].traces()
