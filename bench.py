@@ -536,6 +536,8 @@ def main():
         line["serve"] = serve_leg(dev, args.serve_count, args.serve_rate, nstreams=args.serve_streams,
                                   chunk_us=args.serve_chunk_us)
         line["serve_fused_burst"] = fused_burst_leg(dev)
+        # grids that fit in LDS: one workgroup per shot, whole range in one launch
+        line["serve_fused_burst_lds"] = fused_burst_leg(dev, count=64, n=101, so=4, nt=500)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     if os.environ.get("FDW_BENCH_OPS_OUT"):

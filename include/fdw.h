@@ -241,9 +241,10 @@ int fdw_operator_destroy(fdw_op *op);
  * kind, space order and grid shape (distinct wavefields, models, sources and
  * receivers) over their own step ranges time_m[i]..time_M[i] with one launch
  * per stage and step for all of them (the shot index is a grid dimension);
- * shots with shorter ranges sit out the later launches.  Each shot's results
- * are those of fdw_operator_apply over the same range with the same kernels
- * (bit for bit in 3D and for 2D grids too large for the LDS-resident kernel).
+ * shots with shorter ranges sit out the later launches; 2D isotropic grids
+ * small enough for the LDS-resident kernel run one workgroup per shot over
+ * its whole range in a single launch.  Each shot's results are those of
+ * fdw_operator_apply over the same range, bit for bit.
  * Restrictions: forward mode, no level saving, at most 4 sources with linear
  * weights (fused injection), receivers with linear weights, 3D operators on
  * the streaming kernels.  A batch object owns pinned and device buffers for

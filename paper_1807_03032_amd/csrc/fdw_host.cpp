@@ -879,6 +879,34 @@ static void tti_step_args(const fdw_op *op, int t, TtiArgs &a) {
     a.rec = nullptr;
 }
 
+// Arguments of the LDS-resident 2D isotropic kernel for one apply range.
+static void persist2d_args(const fdw_op *op, int time_m, int time_M, Persist2DArgs &pa) {
+    const fdw_op_desc &d = op->d;
+    const int nsrc = d.src ? d.src->npoint : 0;
+    const int nrec = d.rec ? d.rec->npoint : 0;
+    pa = Persist2DArgs{};
+    pa.g = op->geom;
+    pa.u = d.u->d;
+    pa.slot = op->lay.elems_per_slot;
+    pa.nslots = d.u->nslots;
+    pa.pitch_x = op->lay.pitch_x;
+    pa.m = d.m->d;
+    pa.eta_x = op->d_eta;
+    pa.eta_z = op->d_eta + op->geom.nx + op->geom.ny;
+    pa.dt2 = op->dt2;
+    pa.c = op->coefs;
+    pa.time_m = time_m;
+    pa.time_M = time_M;
+    pa.nsrc = nsrc;
+    pa.src_base = op->d_src_base;
+    pa.src_w = op->d_src_w;
+    pa.src_data = nsrc > 0 ? d.src->data : nullptr;
+    pa.nrec = nrec;
+    pa.rec_base = op->d_rec_base;
+    pa.rec_w = op->d_rec_w;
+    pa.rec_data = nrec > 0 ? d.rec->data : nullptr;
+}
+
 static int timing_event_pair(fdw_op *op, hipEvent_t *a, hipEvent_t *b) {
     while (op->ev_used + 2 > op->ev_pool.size()) {
         hipEvent_t e;
@@ -951,27 +979,8 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
 
     // small 2D isotropic grids: the whole range in one persistent launch
     if (d.kind == FDW_ISO && op->ndim == 2 && op->use_persist2d && !op->save_buf && time_M >= time_m) {
-        Persist2DArgs pa{};
-        pa.g = op->geom;
-        pa.u = d.u->d;
-        pa.slot = E;
-        pa.nslots = d.u->nslots;
-        pa.pitch_x = L.pitch_x;
-        pa.m = d.m->d;
-        pa.eta_x = eta_x;
-        pa.eta_z = eta_z;
-        pa.dt2 = op->dt2;
-        pa.c = op->coefs;
-        pa.time_m = time_m;
-        pa.time_M = time_M;
-        pa.nsrc = nsrc;
-        pa.src_base = op->d_src_base;
-        pa.src_w = op->d_src_w;
-        pa.src_data = nsrc > 0 ? d.src->data : nullptr;
-        pa.nrec = nrec;
-        pa.rec_base = op->d_rec_base;
-        pa.rec_w = op->d_rec_w;
-        pa.rec_data = nrec > 0 ? d.rec->data : nullptr;
+        Persist2DArgs pa;
+        persist2d_args(op, time_m, time_M, pa);
         LaunchEvents ev;
         int st = timing_next(op, ev);
         if (st) return st;
@@ -1335,7 +1344,12 @@ int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, 
     const size_t rs = ndim == 2 ? sizeof(SparseArgs) : 0;
     const size_t off2 = align256(r1 * n), offs = off2 + align256(r2 * n);
     const size_t step_bytes = offs + align256(rs * n);
-    const size_t total = step_bytes * (size_t)nl;
+    // 2D isotropic grids small enough for the LDS-resident kernel: one
+    // workgroup per shot runs its whole range in one launch, with the kernel
+    // body fdw_operator_apply uses (so the same bits)
+    bool persist = ndim == 2 && kind == FDW_ISO;
+    for (int i = 0; i < n; ++i) persist = persist && ops[i]->use_persist2d;
+    const size_t total = persist ? sizeof(Persist2DArgs) * (size_t)n : step_bytes * (size_t)nl;
     if (b->copy_pending) {
         hipError_t e = hipEventSynchronize(b->ev_copy);
         if (e != hipSuccess) return fail_hip(e, "batch_apply: waiting for the previous record copy");
@@ -1357,6 +1371,17 @@ int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, 
         if (e == hipSuccess) e = hipMalloc((void **)&b->d_stage, cap);
         if (e != hipSuccess) return fail(FDW_ERR_NOMEM, "batch_apply: record buffers: %s", hipGetErrorString(e));
         b->cap = cap;
+    }
+    if (persist) {
+        auto *pa = reinterpret_cast<Persist2DArgs *>(b->h_stage);
+        for (int i = 0; i < n; ++i) persist2d_args(ops[i], time_m[i], time_M[i], pa[i]);
+        hipError_t e = hipMemcpyAsync(b->d_stage, b->h_stage, total, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_copy, s);
+        if (e != hipSuccess) return fail_hip(e, "batch_apply: record upload");
+        b->copy_pending = true;
+        e = launch_iso2d_persistent_multi(R, o0->geom, reinterpret_cast<const Persist2DArgs *>(b->d_stage), n, s);
+        if (e != hipSuccess) return fail_hip(e, "batch_apply: persistent 2D launch");
+        return FDW_OK;
     }
     // pack the records of every launch
     std::memset(b->h_stage, 0, total);

@@ -198,6 +198,9 @@ hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream
 hipError_t launch_inject(const SparseArgs &a, hipStream_t s);
 hipError_t launch_interp(const SparseArgs &a, hipStream_t s);
 hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s, const LaunchEvents &ev);
+// Several shots of one geometry (shots: device array of n argument records),
+// one workgroup each.
+hipError_t launch_iso2d_persistent_multi(int R, const Geom &g, const Persist2DArgs *shots, int n, hipStream_t s);
 hipError_t launch_iso2d_tb(int R, const TB2DArgs &a, hipStream_t s, const LaunchEvents &ev);
 // grad += -nu [(u+ - 2u + u-)/dt^2 + eta (u+ - u-)/(2 dt)] over the domain
 struct GradArgs {

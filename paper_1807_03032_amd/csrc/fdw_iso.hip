@@ -102,7 +102,7 @@ struct IsoOp {
 // (the last nslots levels, each in its slot).
 // ---------------------------------------------------------------------------
 template <int R, int PPT, bool HALO>
-__global__ void __launch_bounds__(1024) iso2d_persistent(Persist2DArgs a) {
+__device__ __forceinline__ void iso2d_persistent_body(const Persist2DArgs &a) {
     constexpr bool kCacheCoef = PPT <= 16;
     // LDS level: (nz + 2R) x (nx + 2R) with a zero halo when HALO, else nz x nx
     // with neighbours outside the domain read as zero
@@ -207,6 +207,18 @@ __global__ void __launch_bounds__(1024) iso2d_persistent(Persist2DArgs a) {
         }
         // LDS is only read from here to the first barrier of the next step
     }
+}
+
+template <int R, int PPT, bool HALO>
+__global__ void __launch_bounds__(1024) iso2d_persistent(Persist2DArgs a) {
+    iso2d_persistent_body<R, PPT, HALO>(a);
+}
+
+// Shots of one geometry, one workgroup each (blockIdx.x selects the shot's
+// arguments); each runs its own step range.
+template <int R, int PPT, bool HALO>
+__global__ void __launch_bounds__(1024) iso2d_persistent_multi(const Persist2DArgs *__restrict__ shots) {
+    iso2d_persistent_body<R, PPT, HALO>(shots[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,6 +412,41 @@ static hipError_t launch_iso2d_persistent_r(const Persist2DArgs &a, hipStream_t 
     const size_t halo = sizeof(float) * (size_t)(a.g.nx + 2 * R) * (size_t)(a.g.nz + 2 * R);
     if (halo <= (size_t)kPersist2DMaxLds) return launch_iso2d_persistent_h<R, true>(a, halo, s, ev);
     return launch_iso2d_persistent_h<R, false>(a, sizeof(float) * (size_t)a.g.nx * a.g.nz, s, ev);
+}
+
+template <int R, bool HALO>
+static hipError_t launch_iso2d_persistent_multi_h(const Geom &g, const Persist2DArgs *shots, int n, size_t lds,
+                                                  hipStream_t s) {
+    const int ppt = (g.nx * g.nz + 1023) / 1024;
+#define P2M(PPT_)                                                                                         \
+    {                                                                                                     \
+        hipError_t e = hipFuncSetAttribute((const void *)iso2d_persistent_multi<R, PPT_, HALO>,          \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);         \
+        if (e != hipSuccess) return e;                                                                    \
+        hipLaunchKernelGGL((iso2d_persistent_multi<R, PPT_, HALO>), dim3((unsigned)n), dim3(1024), lds, s, \
+                           shots);                                                                        \
+        return hipGetLastError();                                                                         \
+    }
+    if (ppt <= 8) P2M(8)
+    if (ppt <= 16) P2M(16)
+    if (ppt <= 24) P2M(24)
+    if (ppt <= 40) P2M(40)
+#undef P2M
+    return hipErrorInvalidValue;
+}
+
+template <int R>
+static hipError_t launch_iso2d_persistent_multi_r(const Geom &g, const Persist2DArgs *shots, int n, hipStream_t s) {
+    const size_t halo = sizeof(float) * (size_t)(g.nx + 2 * R) * (size_t)(g.nz + 2 * R);
+    if (halo <= (size_t)kPersist2DMaxLds) return launch_iso2d_persistent_multi_h<R, true>(g, shots, n, halo, s);
+    return launch_iso2d_persistent_multi_h<R, false>(g, shots, n, sizeof(float) * (size_t)g.nx * g.nz, s);
+}
+
+hipError_t launch_iso2d_persistent_multi(int R, const Geom &g, const Persist2DArgs *shots, int n, hipStream_t s) {
+    if ((size_t)g.nx * g.nz * sizeof(float) > (size_t)kPersist2DMaxLds || n <= 0) return hipErrorInvalidValue;
+#define P2MR(r) launch_iso2d_persistent_multi_r<r>(g, shots, n, s)
+    FDW_DISPATCH_R(R, P2MR)
+#undef P2MR
 }
 
 hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s, const LaunchEvents &ev) {

@@ -32,6 +32,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -74,6 +75,7 @@ struct Chunk {
 struct Bucket {
     std::string key;
     bool large = false;  // one shot fills the chip (see kLargePoints)
+    int64_t chunks_launched = 0;
     hipStream_t stream = nullptr;
     fdw_batch *batch[2] = {nullptr, nullptr};
     int next_batch = 0;
@@ -103,7 +105,6 @@ struct Shot {
     // results (pinned host memory)
     float *h_rec = nullptr;
     float *h_field = nullptr;  // padded last level of u / p when kept
-    Bucket *bucket = nullptr;
     bool released = false;     // results fetched; freed with the graveyard
     std::string error;         // why the shot failed at admission
 };
@@ -239,12 +240,19 @@ int64_t footprint_bytes(const Sizes &z) {
 }
 
 // ------------------------------------------------------------- admission
-std::string bucket_key(const fdw_shot_desc &d) {
+// Shots of one kind, grid and space order share a bucket (fused launches).  A
+// shot that fills the GPU alone gains nothing from fusion (the multi-shot
+// kernels read the operator from a record and are slower), so it gets a
+// bucket of its own and runs the single-shot kernels.
+std::string bucket_key(const fdw_shot_desc &d, int64_t ticket) {
+    int64_t npts = 1;
+    for (int a = 0; a < d.ndim; ++a) npts *= d.shape[a];
     char buf[256];
-    snprintf(buf, sizeof(buf), "%d/%d/%lldx%lldx%lld/so%d/h%.9g,%.9g,%.9g", d.kind, d.ndim, (long long)d.shape[0],
-             (long long)d.shape[1], (long long)(d.ndim == 3 ? d.shape[2] : 1), d.space_order,
+    snprintf(buf, sizeof(buf), "%d/%d/%lldx%lldx%lld/so%d/h%.9g,%.9g,%.9g/%lld", d.kind, d.ndim,
+             (long long)d.shape[0], (long long)d.shape[1], (long long)(d.ndim == 3 ? d.shape[2] : 1), d.space_order,
              d.extent[0] / (double)(d.shape[0] - 1), d.extent[1] / (double)(d.shape[1] - 1),
-             d.ndim == 3 ? d.extent[2] / (double)(d.shape[2] - 1) : 0.0);
+             d.ndim == 3 ? d.extent[2] / (double)(d.shape[2] - 1) : 0.0,
+             (long long)(npts >= kLargePoints ? ticket : 0));
     return buf;
 }
 
@@ -275,7 +283,7 @@ int admit(fdw_server *sv, Shot *s) {
     Sizes z;
     int st = shot_sizes(&d, &z);
     if (st) return st;
-    const std::string key = bucket_key(d);
+    const std::string key = bucket_key(d, s->ticket);
     auto bit = sv->buckets.find(key);
     Bucket *b = nullptr;
     if (bit == sv->buckets.end()) {
@@ -287,7 +295,7 @@ int admit(fdw_server *sv, Shot *s) {
         // other (they only compete for the caches): large buckets advance one at
         // a time, in creation order, on stream 0; small ones share the other
         // streams and fill the gaps.
-        nb->large = npts >= kLargePoints && sv->nstreams > 1;
+        nb->large = npts >= kLargePoints;
         nb->stream = nb->large ? sv->streams[0] : sv->streams[sv->nstreams > 1 ? 1 + sv->next_stream++ % (sv->nstreams - 1) : 0];
         for (auto &bt : nb->batch) {
             st = fdw_batch_create(&bt);
@@ -411,7 +419,6 @@ int admit(fdw_server *sv, Shot *s) {
     s->state = FDW_SHOT_RUNNING;
     s->t_admit = sv->now();
     s->t_next = 0;
-    s->bucket = b;
     b->active.push_back(s);
     sv->used += s->footprint;
     sv->admitted++;
@@ -477,6 +484,7 @@ int launch_chunk(fdw_server *sv, Bucket *b) {
     hipError_t e = hipEventRecord(c.ev, b->stream);
     if (e != hipSuccess) return sfail_hip(e, "server: hipEventRecord");
     b->inflight.push_back(std::move(c));
+    b->chunks_launched++;
     sv->chunks++;
     return FDW_OK;
 }
@@ -567,13 +575,30 @@ int fdw_server_progress(fdw_server *sv, int *queued, int *running) {
             b->inflight.pop_front();
         }
     }
+    // a large bucket holds one shot: drop it once that shot's work is done
+    for (auto it = sv->buckets.begin(); it != sv->buckets.end();) {
+        Bucket *b = it->second.get();
+        if (b->large && b->active.empty() && b->inflight.empty()) {
+            for (hipEvent_t e : b->free_events) (void)hipEventDestroy(e);
+            for (fdw_batch *bt : b->batch) fdw_batch_destroy(bt);
+            sv->large_order.erase(std::remove(sv->large_order.begin(), sv->large_order.end(), b),
+                                  sv->large_order.end());
+            it = sv->buckets.erase(it);
+        } else {
+            ++it;
+        }
+    }
     // 2. admissions, in arrival order; requests that do not fit wait.  At most
     // a few milliseconds of host work per call: the chunks of what is already
     // admitted are launched below, so the GPU starts on the first requests of
     // a burst while the later ones are still being uploaded.
     const double t_adm = sv->now();
+    bool sliced = false;  // queued requests left unexamined for lack of time
     for (auto it = sv->queue.begin(); it != sv->queue.end();) {
-        if (sv->now() - t_adm > kAdmitSliceSeconds) break;
+        if (sv->now() - t_adm > kAdmitSliceSeconds) {
+            sliced = true;
+            break;
+        }
         Shot *s = *it;
         if (sv->used + s->footprint > sv->budget) {
             ++it;
@@ -603,7 +628,12 @@ int fdw_server_progress(fdw_server *sv, int *queued, int *running) {
         it = sv->queue.erase(it);
     }
     // 3. next chunk of every bucket with running shots (two chunks in flight);
-    // of the large buckets only the oldest one with running shots
+    // of the large buckets only the oldest one with running shots.  While
+    // admissions are cut short, a bucket that has not started yet waits for
+    // the queued requests of its own shape, so that they share its launches.
+    std::set<std::string> pending_keys;
+    if (sliced)
+        for (Shot *q : sv->queue) pending_keys.insert(bucket_key(q->d, q->ticket));
     Bucket *large_now = nullptr;
     for (Bucket *b : sv->large_order)
         if (!b->active.empty()) {
@@ -613,7 +643,8 @@ int fdw_server_progress(fdw_server *sv, int *queued, int *running) {
     int nrun = 0;
     for (auto &kv : sv->buckets) {
         Bucket *b = kv.second.get();
-        if (!b->active.empty() && b->inflight.size() < 2 && (!b->large || b == large_now)) {
+        const bool gather = b->inflight.empty() && b->chunks_launched == 0 && pending_keys.count(b->key) > 0;
+        if (!b->active.empty() && b->inflight.size() < 2 && (!b->large || b == large_now) && !gather) {
             const double tl = sv->now();
             int st = launch_chunk(sv, b);
             sv->launch_s += sv->now() - tl;
