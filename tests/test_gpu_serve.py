@@ -238,3 +238,23 @@ def test_batch_rejects_what_it_cannot_fuse(torch_dev):
 def torch_sync():
     import torch
     torch.cuda.synchronize()
+
+
+def test_server_large_shots_run_alone(torch_dev):
+    """Shots of 4 Mi grid points or more get buckets of their own (even with
+    one shape) and run the single-shot kernels one at a time; their buckets
+    are dropped when they finish.  Results equal the plain per-shot solves bit
+    for bit, and the small request beside them equals its alone-served self."""
+    reqs = [W.serve_problem("iso", 3, 162, 4, 24, seed=90 + k, nbl=8) for k in range(2)]
+    reqs.append(W.serve_problem("iso", 2, 201, 8, 30, seed=92, nbl=10))
+    assert all(np.prod(p.shape) >= 1 << 22 for p in reqs[:2])
+    say("large shots")
+    out, stats = serve_all(reqs, stagger=1)
+    assert stats["completed"] == 3 and stats["buckets"] == 1, stats
+    for i in (0, 1):
+        tr, f = run_alone(reqs[i], torch_dev)
+        np.testing.assert_array_equal(out[i][0], tr)
+        np.testing.assert_array_equal(out[i][1], f["u"][1])
+    alone = serve_all([reqs[2]])[0][0]
+    np.testing.assert_array_equal(out[2][0], alone[0])
+    np.testing.assert_array_equal(out[2][1], alone[1])
