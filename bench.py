@@ -1,8 +1,9 @@
-"""Throughput benchmark of the forward wave-equation operator on one MI355X.
+"""Throughput benchmark of the forward wave-equation operators on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--tti]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-tti] [--no-iso512] [--no-serve] [--no-attainable]
 
-Workload (default): 3D isotropic acoustic, 256^3 grid, h = 10 m, two-layer
+Headline workload: 3D isotropic acoustic, 256^3 grid, h = 10 m, two-layer
 velocity 1500/2500 m/s, space order 8, 40-point damping layer, 15 Hz Ricker
 source, 256 x 256 receiver plane with trilinear interpolation, FP32.  A
 "step" is one time step of the whole path: stencil update with fused source
@@ -12,8 +13,14 @@ workload's full time axis.  Inputs are resident in HBM before timing starts.
 Prints ONE JSON line with the throughput in GPts/s (grid points x steps / s),
 the HBM roofline of the dominant stencil kernel (algorithmic bytes per launch
 over its average launch time, from HIP events around every launch in the
-timed region) and the FP64 oracle timed on the host cores on a bounded
-sample of the same workload.
+timed region; also as a fraction of the attainable bandwidth measured by the
+library's triad probe in the same run) and the FP64 oracle timed on the host
+cores on a bounded sample of the same workload.  The same line carries, by
+default, K steps of the 512^3 TTI so = 12 workload (`tti`), K steps of the
+isotropic so = 8 workload at 512^3 (`iso512`, working set beyond the
+Infinity Cache), the copy/triad probe rates (`attainable`) and the served
+shot stream (`serve`: p50/p99 latency, aggregate GPts/s, burst against
+sequential plain solves).
 """
 import argparse
 import json
@@ -35,7 +42,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=400, help="oracle steps of the bounded CPU sample")
-    ap.add_argument("--tti", action="store_true", help="also time the 512^3 TTI so=12 operator")
+    ap.add_argument("--no-tti", action="store_true", help="skip the 512^3 TTI so=12 leg")
+    ap.add_argument("--no-iso512", action="store_true", help="skip the 512^3 isotropic so=8 leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served shot-stream leg")
+    ap.add_argument("--no-attainable", action="store_true", help="skip the copy/triad bandwidth probe")
+    ap.add_argument("--serve-extra", action="store_true",
+                    help="also run the same-shape fused bursts (2D 401^2 and LDS-resident 101^2 shots)")
     ap.add_argument("--tti-n", type=int, default=512, help="grid points per axis of the TTI leg (512: the workload)")
     ap.add_argument("--tti-steps", type=int, default=0, help="steps of the TTI leg (0: the workload's 800)")
     ap.add_argument("--nslots", type=int, default=2, choices=(2, 3),
@@ -442,17 +454,57 @@ def load_traffic(kind, desc):
     return e.get("bytes_per_launch")
 
 
-def roofline(prob, kms, launches, alg_bytes, traffic=None):
+def roofline(prob, kms, launches, alg_bytes, traffic=None, attainable=None):
     if launches <= 0 or kms <= 0:
         return None
     avg_s = kms / launches / 1e3
     per_launch = alg_bytes * prob.npoints
     achieved = per_launch / avg_s / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": round(traffic) if traffic is not None else None,
-            "algorithmic_bytes": round(per_launch),
-            "kernel_avg_us": round(avg_s * 1e6, 2), "bytes_per_point": alg_bytes}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": round(traffic) if traffic is not None else None,
+           "algorithmic_bytes": round(per_launch),
+           "kernel_avg_us": round(avg_s * 1e6, 2), "bytes_per_point": alg_bytes}
+    if attainable:
+        out["attainable"] = round(attainable, 1)
+        out["frac_attainable"] = round(achieved / attainable, 4)
+    return out
+
+
+def attainable_bandwidth(device, mib=1024, reps=20):
+    """HBM bandwidth of the library's copy and triad probes (the paper's
+    STREAM-triad convention for the attainable peak) on arrays of `mib` MiB,
+    far beyond the 256 MB Infinity Cache: best per-launch rate over `reps`
+    launches, each bracketed by events on the launch stream."""
+    import torch
+
+    from paper_1807_03032_amd import fdw
+
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, device=device)
+    b = torch.full((n,), 0.5, device=device)
+    c = torch.empty(n, device=device)
+    st = torch.cuda.current_stream(device)
+    out = {"array_mib": mib}
+    for kind, name, nbytes in ((0, "copy", 8 * n), (1, "triad", 12 * n)):
+        for _ in range(3):
+            fdw.fdw_bandwidth_probe(kind, c.data_ptr(), a.data_ptr(), b.data_ptr(), 3.0, n, st.cuda_stream)
+        best = None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fdw.fdw_bandwidth_probe(kind, c.data_ptr(), a.data_ptr(), b.data_ptr(), 3.0, n, st.cuda_stream)
+            e1.record(st)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[f"{name}_gbs"] = round(nbytes / (best * 1e-3) / 1e9, 1)
+    expect = 1.0 + 3.0 * 0.5
+    assert float(c[0]) == expect and float(c[-1]) == expect, "triad probe result"
+    del a, b, c
+    torch.cuda.empty_cache()
+    out["attainable_gbs"] = out["triad_gbs"]
+    return out
 
 
 def main():
@@ -488,8 +540,10 @@ def main():
     dev = torch.device("cuda:0")
     if args.calib_copy:
         calib_copy(dev)
-    prob = W.config_3d_iso_256(nt=max(1000, args.steps) if args.steps > 1000 else 1000)
     steps, warmup = args.steps, args.warmup
+    att = None if args.no_attainable else attainable_bandwidth(dev)
+    att_gbs = att["attainable_gbs"] if att else None
+    prob = W.config_3d_iso_256(nt=max(1000, args.steps) if args.steps > 1000 else 1000)
     wall, kms, launches, desc, alg_bytes, tr, f = time_shot(prob, steps, warmup, dev, args.nslots)
     desc = f"{desc} slots={args.nslots}"
     value = prob.npoints * steps / wall / 1e9
@@ -510,31 +564,52 @@ def main():
                                "15 Hz Ricker source, 256x256 receiver plane (trilinear), 1000 steps",
                    "grid": list(prob.shape), "space_order": prob.so, "nt": prob.nt, "kernel": desc,
                    "wavefield_storage": "in-place leapfrog, 2 slots" if args.nslots == 2 else "modulo-3 buffer"},
-        "roofline": roofline(prob, kms, launches, alg_bytes, load_traffic("iso", desc)),
+        "roofline": roofline(prob, kms, launches, alg_bytes, load_traffic("iso", desc), att_gbs),
     }
     ops_seen = [{"desc": desc, "source_hash": source_hash("iso"), "kernel_match": ["IsoOp", "iso_naive"]}]
     par = parity_vs_stored("3d_iso_256", prob, steps, tr, f)
     if par is not None:
         line["parity_rel_l2_sampled"] = par
-    if args.tti:
-        pt = W.config_3d_tti_512(nt=args.tti_steps or None, n=args.tti_n)
-        w2, k2, l2, d2, b2, tr2, f2 = time_shot(pt, pt.nt, min(20, pt.nt), dev)
-        line["tti"] = {"workload": f"3D TTI {args.tti_n}^3, h=12.5 m, so=12, nbl=40, {pt.nt} steps", "kernel": d2,
-                       "value": round(pt.npoints * pt.nt / w2 / 1e9, 3), "unit": "GPts/s",
-                       "roofline": roofline(pt, k2, l2, b2, load_traffic("tti", d2))}
+    del tr, f
+    if att:
+        line["attainable"] = att
+    if not args.no_iso512:
+        # working set far beyond the 256 MB Infinity Cache: the off-cache rate
+        p5 = W.config_3d_iso_256(nt=max(1000, steps), n=512)
+        w5, k5, l5, d5, b5, _, _ = time_shot(p5, steps, warmup, dev, 2)
+        d5 = f"{d5} slots=2"
+        line["iso512"] = {"workload": "3D isotropic acoustic 512^3, h=10 m, v 1500/2500 m/s two-layer, so=8, nbl=40, "
+                                      "15 Hz Ricker source, 512x512 receiver plane",
+                          "kernel": d5, "steps": steps, "value": round(p5.npoints * steps / w5 / 1e9, 3),
+                          "unit": "GPts/s", "ms_per_step": round(w5 * 1e3 / steps, 5),
+                          "roofline": roofline(p5, k5, l5, b5, load_traffic("iso", d5), att_gbs)}
+        ops_seen.append({"desc": d5, "source_hash": source_hash("iso"), "kernel_match": ["IsoOp", "iso_naive"]})
+        del p5
+    if not args.no_tti:
+        tsteps = args.tti_steps or steps
+        pt = W.config_3d_tti_512(nt=max(800, tsteps), n=args.tti_n)
+        w2, k2, l2, d2, b2, tr2, f2 = time_shot(pt, tsteps, min(warmup, 20), dev)
+        line["tti"] = {"workload": f"3D TTI {args.tti_n}^3, h=12.5 m, so=12, nbl=40, 800 steps, smooth random "
+                                   f"v/eps/delta/theta/phi", "kernel": d2, "steps": tsteps,
+                       "value": round(pt.npoints * tsteps / w2 / 1e9, 3), "unit": "GPts/s",
+                       "ms_per_step": round(w2 * 1e3 / tsteps, 5),
+                       "roofline": roofline(pt, k2, l2, b2, load_traffic("tti", d2), att_gbs)}
         ops_seen.append({"desc": d2, "source_hash": source_hash("tti"), "kernel_match": ["TtiS1Op", "TtiS2Op", "tti_naive"]})
-        p2 = parity_vs_stored("3d_tti_512", pt, pt.nt, tr2, f2) if (args.tti_n, pt.nt) == (512, 800) else None
+        p2 = parity_vs_stored("3d_tti_512", pt, tsteps, tr2, f2) if (args.tti_n, pt.nt, tsteps) == (512, 800, 800) \
+            else None
         if p2 is not None:
             line["tti"]["parity_rel_l2_sampled"] = p2
+        del pt, tr2, f2
     if args.adjoint:
         line["adjoint"] = adjoint_leg(dev)
     if args.save_every > 0:
         line["snapshots"] = snapshot_leg(prob, args.save_every, dev)
     if args.tb2d:
         line["tb2d"] = tb2d_leg(dev)
-    if args.serve:
+    if not args.no_serve:
         line["serve"] = serve_leg(dev, args.serve_count, args.serve_rate, nstreams=args.serve_streams,
                                   chunk_us=args.serve_chunk_us)
+    if args.serve_extra:
         line["serve_fused_burst"] = fused_burst_leg(dev)
         # grids that fit in LDS: one workgroup per shot, whole range in one launch
         line["serve_fused_burst_lds"] = fused_burst_leg(dev, count=64, n=101, so=4, nt=500)
@@ -543,7 +618,6 @@ def main():
     if os.environ.get("FDW_BENCH_OPS_OUT"):
         json.dump(ops_seen, open(os.environ["FDW_BENCH_OPS_OUT"], "w"))
     print(json.dumps(line), flush=True)
-
 
 if __name__ == "__main__":
     main()

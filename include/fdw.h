@@ -6,11 +6,11 @@
  * The calls mirror the problem statement of arXiv 1807.03032 (Devito):
  *   Grid(shape, extent, origin)                 -> fdw_grid_create        (Section 3.1)
  *   Function / TimeFunction(space_order, ...)   -> fdw_function_bind,
- *                                                  fdw_timefunction_bind  (Section 3.1, 3.5)
- *   domain / halo / padding regions             -> fdw_field_layout       (Section 3.6)
+ *                                                  fdw_timefunction_bind  (Section 3.1, 3.4)
+ *   domain / halo / padding regions             -> fdw_field_layout       (Section 3.5)
  *   SparseTimeFunction(coordinates), inject,
- *   interpolate                                 -> fdw_sparse_bind        (Section 3.3)
- *   PrecomputedSparseFunction                   -> fdw_sparse_bind_precomputed (Section 3.3)
+ *   interpolate                                 -> fdw_sparse_bind        (Section 3.2)
+ *   PrecomputedSparseFunction                   -> fdw_sparse_bind_precomputed (Section 3.2)
  *   Operator(eqs) ... op.apply(time=...)        -> fdw_operator_create,
  *                                                  fdw_operator_apply     (Section 4 intro, 4.8)
  *
@@ -64,14 +64,14 @@ typedef struct fdw_sparse fdw_sparse;
 typedef struct fdw_op fdw_op;
 
 /* Memory layout of one field (one time slot) for a grid and space order.
- * Section 3.6 (domain, halo, padding): the halo is R = space_order/2 points
+ * Section 3.5 (domain, halo, padding): the halo is R = space_order/2 points
  * on every side of every axis and must hold zeros (Dirichlet, Section 7.2);
  * padding aligns logical x = 0 of every row to 128 bytes.
  *   3D element (x, y, z) at  origin_offset + (z * pitch_y + y) * pitch_x + x
  *   2D element (x, z)    at  origin_offset +  z * pitch_x + x
  * A field occupies elems_per_slot floats; a TimeFunction with time_order 2
  * holds nslots = 3 slots back to back, logical time level t in slot t mod 3
- * (Section 3.5: u[t % 3]; level -1 lives in slot 2), or nslots = 2 slots with
+ * (Section 3.4: u[t % 3]; level -1 lives in slot 2), or nslots = 2 slots with
  * level t in slot t mod 2 (in-place leapfrog storage, see
  * fdw_timefunction_bind). */
 typedef struct {
@@ -110,7 +110,7 @@ typedef struct {
 } fdw_op_desc;
 
 /* Operator modes.  FDW_ADJOINT builds the transpose of the isotropic
- * source-to-receiver map (the adjoint of Section 3.3's injection/interpolation
+ * source-to-receiver map (the adjoint of Section 3.2's injection/interpolation
  * pair, extended to the whole time loop): with nu = (dt^2/m) D^-1 lambda,
  * D = 1 + eta dt/2, the transposed recurrence is the same leapfrog step run
  * backwards in time.  An adjoint operator is the forward one with two changes:
@@ -125,12 +125,12 @@ typedef struct {
 /* Grid(shape, extent, origin), Section 3.1.  ndim in {2, 3}; shape[a] >= 2;
  * extent[a] > 0; spacing h_a = extent[a] / (shape[a] - 1).  origin may be
  * NULL (all zeros).  The shape is the computational domain, absorbing layer
- * included (Section 3.6).  Errors: FDW_ERR_ARG. */
+ * included (Section 3.5).  Errors: FDW_ERR_ARG. */
 int fdw_grid_create(int ndim, const int64_t *shape, const double *extent, const double *origin,
                     fdw_grid **out);
 int fdw_grid_destroy(fdw_grid *grid);
 
-/* Layout of a field of this grid at this space order (Section 3.6); pure host
+/* Layout of a field of this grid at this space order (Section 3.5); pure host
  * arithmetic, no device call.  Errors: FDW_ERR_ARG. */
 int fdw_field_layout(const fdw_grid *grid, int space_order, fdw_layout *out);
 
@@ -144,7 +144,7 @@ int fdw_function_bind(fdw_grid *grid, const char *name, float *dptr, int64_t nel
                       fdw_func **out);
 int fdw_function_destroy(fdw_func *f);
 
-/* TimeFunction (Section 3.1, 3.5): a wavefield of time order 2 (time_order
+/* TimeFunction (Section 3.1, 3.4): a wavefield of time order 2 (time_order
  * must be 2) stored in nslots slots, level t in slot t mod nslots:
  *   nslots = 3: the paper's modulo buffer u[t % 3] (time_order + 1 slots);
  *   nslots = 2: in-place leapfrog storage -- step t overwrites level t-1 with
@@ -160,7 +160,7 @@ int fdw_timefunction_bind(fdw_grid *grid, const char *name, float *dptr, int64_t
                           int space_order, int time_order, int nslots, fdw_tfunc **out);
 int fdw_timefunction_destroy(fdw_tfunc *f);
 
-/* SparseTimeFunction (Section 3.3, eq. interp, Listing finject).
+/* SparseTimeFunction (Section 3.2, eq. interp, Listing finject).
  * coords_host: host array [npoint][ndim] of physical coordinates (copied);
  * ddata: device float array [nt][npoint] (time-major), source samples read by
  * injection or receiver samples written by interpolation; may be NULL when
@@ -172,7 +172,7 @@ int fdw_timefunction_destroy(fdw_tfunc *f);
 int fdw_sparse_bind(fdw_grid *grid, const char *name, int npoint, int nt, const double *coords_host,
                     float *ddata, fdw_sparse **out);
 
-/* PrecomputedSparseFunction (Section 3.3: grid points and coefficients
+/* PrecomputedSparseFunction (Section 3.2: grid points and coefficients
  * computed by the caller for a custom interpolation scheme).  Point p is
  * supported on the r^ndim grid points gridpoints[p][a] + j_a, j_a = 0..r-1 on
  * every axis a (axes in grid order, indices of the computational domain), with
@@ -200,7 +200,7 @@ int fdw_sparse_destroy(fdw_sparse *s);
 int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out);
 
 /* Operator application (Section 4.8: the generated entry point; the time loop
- * of Section 4.6: stencil, then injection, inside t).
+ * of Section 4.5: stencil, then injection, inside t).
  * Runs steps t = time_m .. time_M.  Step t computes level t+1 from levels t
  * and t-1 into slot (t+1) mod 3, injects src[t] (dt^2 q / m at each target
  * point) into level t+1 (into p and r for TTI) and writes rec[t][:] by
@@ -213,7 +213,7 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out);
  * Errors: FDW_ERR_ARG (range), FDW_ERR_DEVICE. */
 int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream);
 
-/* Subsampled level saving (Section 3.5, ConditionalDimension / save=): while
+/* Subsampled level saving (Section 3.4, ConditionalDimension / save=): while
  * the isotropic operator runs, every level L >= first_level with
  * (L - first_level) % every == 0 and k = (L - first_level) / every < nlevels
  * is also stored in buf + k * elems_per_slot (same layout; halos untouched).
@@ -293,7 +293,7 @@ int fdw_batch_destroy(fdw_batch *b);
 #define FDW_SHOT_QUEUED 0
 #define FDW_SHOT_RUNNING 1
 #define FDW_SHOT_DONE 2
-#define FDW_SHOT_FAILED 3  /* rejected at admission (operator errors); see fdw_server_fetch */
+#define FDW_SHOT_FAILED 3  /* rejected at admission or a chunk refused (operator errors); see fdw_server_fetch */
 
 typedef struct {
     int kind;                  /* FDW_ISO or FDW_TTI                                     */
@@ -360,6 +360,16 @@ int fdw_operator_kernel_time(fdw_op *op, double *total_ms, int64_t *launches, in
  * algorithmic bytes per grid point per step of the dominant kernel).
  * Writes a NUL-terminated string of at most buflen bytes.  Errors: FDW_ERR_ARG. */
 int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_bytes_per_point);
+
+/* Bandwidth probe (measurement support; Section 7.1 takes the STREAM triad
+ * rate as the attainable memory bandwidth of its roofline plots): one launch
+ * of a plain streaming kernel over n floats on `stream`.  kind 0: copy
+ * dst = a (reads and writes 4 n bytes each); kind 1: triad dst = a + s b
+ * (reads 8 n, writes 4 n bytes).  dst, a, b: device buffers owned by the
+ * caller, 16-byte aligned, n a multiple of 4 (b unused for kind 0).
+ * Asynchronous.  Errors: FDW_ERR_ARG (NULL pointer, misalignment, n not a
+ * multiple of 4, unknown kind), FDW_ERR_DEVICE. */
+int fdw_bandwidth_probe(int kind, float *dst, const float *a, const float *b, float s, int64_t n, void *stream);
 
 /* Largest stable dt for the leapfrog scheme at this order (von Neumann bound
  * of the order-so Laplacian: dt <= 2 / (v_eff sqrt(sum_a lambda_so / h_a^2)),

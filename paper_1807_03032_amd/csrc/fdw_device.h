@@ -1,5 +1,5 @@
 // Device-side building blocks shared by the HIP kernels of the wave-equation
-// operators (arXiv 1807.03032; Section 7.2 test cases, Section 3.3 sparse
+// operators (arXiv 1807.03032; Section 7.2 test cases, Section 3.2 sparse
 // points): leapfrog update, Laplacian, fused source injection, and the 3D
 // z-streaming engine that the isotropic step and both TTI stages run on.
 //

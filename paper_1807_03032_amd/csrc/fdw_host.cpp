@@ -3,9 +3,9 @@
 // sparse-point preprocessing and the per-step launch sequence.
 //
 // Paper: arXiv 1807.03032.  Grid / Function / TimeFunction /
-// SparseTimeFunction follow Section 3.1; domain/halo/padding Section 3.6;
-// interpolation and injection Section 3.3 (eq. interp, Listing finject);
-// the operator and its time loop Sections 4 and 4.6.
+// SparseTimeFunction follow Section 3.1; domain/halo/padding Section 3.5;
+// interpolation and injection Section 3.2 (eq. interp, Listing finject);
+// the operator and its time loop Sections 4 and 4.5.
 #include "fdw.h"
 #include "fdw_internal.h"
 
@@ -144,7 +144,7 @@ struct fdw_op {
 };
 
 // ---------------------------------------------------------------------------
-// Layout (Section 3.6: domain, halo, padding)
+// Layout (Section 3.5: domain, halo, padding)
 // ---------------------------------------------------------------------------
 static bool valid_so(int so) { return so >= 2 && so <= FDW_MAX_SO && (so % 2) == 0; }
 
@@ -1166,6 +1166,17 @@ int fdw_gradient_accumulate(fdw_op *op, const float *nu, const float *u_next, co
     return FDW_OK;
 }
 
+int fdw_bandwidth_probe(int kind, float *dst, const float *a, const float *b, float s, int64_t n, void *stream) {
+    if (!dst || !a || (kind == 1 && !b)) return fail(FDW_ERR_ARG, "bandwidth_probe: NULL buffer");
+    if (kind != 0 && kind != 1) return fail(FDW_ERR_ARG, "bandwidth_probe: kind must be 0 (copy) or 1 (triad)");
+    if (n < 0 || n % 4 != 0) return fail(FDW_ERR_ARG, "bandwidth_probe: n = %lld is not a multiple of 4", (long long)n);
+    if (((uintptr_t)dst | (uintptr_t)a | (uintptr_t)b) % 16 != 0)
+        return fail(FDW_ERR_ARG, "bandwidth_probe: buffers must be 16-byte aligned");
+    hipError_t e = launch_bandwidth_probe(kind, dst, a, b, s, n, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "bandwidth_probe: launch");
+    return FDW_OK;
+}
+
 int fdw_sync(fdw_op *op) {
     if (!op) return fail(FDW_ERR_ARG, "sync: NULL op");
     hipError_t e = hipDeviceSynchronize();
@@ -1300,6 +1311,25 @@ int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, 
     const fdw_op *o0 = ops[0];
     if (!o0) return fail(FDW_ERR_ARG, "batch_apply: NULL op");
     const int kind = o0->d.kind, ndim = o0->ndim, R = o0->R;
+    // A single 3D shot runs the single-shot kernels, which take the operator
+    // and its field pointers as kernel arguments (the multi-shot kernels read
+    // them from a record: 2.6 % slower at space order 16, up to 12 % for the
+    // isotropic step); the results are the same bit for bit.  Only the checks
+    // of the batch's own contract apply (forward, no saving, range, sparse
+    // time axes): what only the multi-shot kernels need (fused sources, linear
+    // receivers, fields below 4 GiB) does not.
+    if (n == 1 && ndim == 3) {
+        const fdw_op_desc &d = o0->d;
+        if (d.mode != FDW_FORWARD || o0->save_buf)
+            return fail(FDW_ERR_ARG, "batch_apply: op 0: forward operators without level saving only");
+        if (time_m[0] < 0 || time_M[0] < time_m[0] - 1)
+            return fail(FDW_ERR_ARG, "batch_apply: op 0: invalid range %d..%d", time_m[0], time_M[0]);
+        const int nsrc = d.src ? d.src->npoint : 0, nrec = d.rec ? d.rec->npoint : 0;
+        if ((nsrc > 0 && time_M[0] >= d.src->nt) || (nrec > 0 && time_M[0] >= d.rec->nt))
+            return fail(FDW_ERR_ARG, "batch_apply: op 0: time_M = %d beyond the sparse time axis", time_M[0]);
+        if (time_M[0] < time_m[0]) return FDW_OK;
+        return fdw_operator_apply(ops[0], time_m[0], time_M[0], stream);
+    }
     int K = 0;
     int64_t lanes = 0;
     for (int i = 0; i < n; ++i) {
@@ -1330,11 +1360,6 @@ int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, 
         lanes = std::max(lanes, (int64_t)nrec * (1 << ndim));
     }
     if (K == 0) return FDW_OK;
-    // A single 3D shot runs the single-shot kernels, which take the operator
-    // and its field pointers as kernel arguments (the multi-shot kernels read
-    // them from a record: 2.6 % slower at space order 16, up to 12 % for the
-    // isotropic step); the results are the same bit for bit.
-    if (n == 1 && ndim == 3) return fdw_operator_apply(ops[0], time_m[0], time_M[0], stream);
     hipStream_t s = (hipStream_t)stream;
     // 3D: receivers of step t are sampled in the launch of step t + 1, so one
     // more launch samples the last step; 2D: a sampling launch after each step

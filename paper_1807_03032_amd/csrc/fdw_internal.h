@@ -1,5 +1,5 @@
 // Internal declarations shared by the host ABI (fdw_host.cpp) and the HIP
-// kernels (fdw_kernels.hip).  Not part of the public ABI.
+// kernels (fdw_*.hip).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_ext.h>
@@ -201,6 +201,13 @@ hipError_t launch_iso2d_persistent(int R, const Persist2DArgs &a, hipStream_t s,
 // Several shots of one geometry (shots: device array of n argument records),
 // one workgroup each.
 hipError_t launch_iso2d_persistent_multi(int R, const Geom &g, const Persist2DArgs *shots, int n, hipStream_t s);
+// the two LDS forms of the persistent kernel (zero halo around the level in
+// LDS, or the level alone): one shot (one != NULL, its arguments by value) or
+// n shots (shots: device array of argument records)
+hipError_t launch_iso2d_persistent_halo(int R, const Persist2DArgs *one, const Geom &g, const Persist2DArgs *shots,
+                                        int n, size_t lds, hipStream_t s, const LaunchEvents &ev);
+hipError_t launch_iso2d_persistent_nohalo(int R, const Persist2DArgs *one, const Geom &g, const Persist2DArgs *shots,
+                                          int n, size_t lds, hipStream_t s, const LaunchEvents &ev);
 hipError_t launch_iso2d_tb(int R, const TB2DArgs &a, hipStream_t s, const LaunchEvents &ev);
 // grad += -nu [(u+ - 2u + u-)/dt^2 + eta (u+ - u-)/(2 dt)] over the domain
 struct GradArgs {
@@ -213,6 +220,11 @@ struct GradArgs {
 hipError_t launch_gradient(int ndim, const GradArgs &a, hipStream_t s);
 hipError_t launch_zero_halo(int ndim, const Geom &g, int R, int64_t pitch_x, int64_t pitch_y,
                             int64_t planes, float *base, hipStream_t s);
+
+// Bandwidth probes: kind 0 copies dst = a, kind 1 is the triad dst = a + s b
+// (n floats, a multiple of 4, 16-byte aligned pointers).
+hipError_t launch_bandwidth_probe(int kind, float *dst, const float *a, const float *b, float s, int64_t n,
+                                  hipStream_t st);
 
 // Human-readable description of the launch plan of the dominant kernel.
 const char *iso_kernel_name(int ndim, IsoVariant v, const Geom &g);

@@ -106,7 +106,7 @@ struct Shot {
     float *h_rec = nullptr;
     float *h_field = nullptr;  // padded last level of u / p when kept
     bool released = false;     // results fetched; freed with the graveyard
-    std::string error;         // why the shot failed at admission
+    std::string error;         // why the shot failed (admission or a refused chunk)
 };
 
 }  // namespace
@@ -437,6 +437,25 @@ void retire(fdw_server *sv, Shot *s) {
     sv->graveyard.push_back(s);
 }
 
+// A running shot whose chunk the library refuses: it fails alone, its device
+// blocks go back to the pool once the bucket's chunks in flight (which may
+// still read them) have completed.
+void fail_running(fdw_server *sv, Bucket *b, const std::string &why) {
+    for (Chunk &c : b->inflight) (void)hipEventSynchronize(c.ev);
+    for (Shot *s : b->active) {
+        for (auto &pb : s->dev) pool_release(sv, pb.first, pb.second);
+        s->dev.clear();
+        s->d_field[0] = s->d_field[1] = nullptr;
+        s->d_src = s->d_rec = nullptr;
+        sv->used -= s->footprint;
+        s->state = FDW_SHOT_FAILED;
+        s->error = why;
+        s->t_done = sv->now();
+        sv->graveyard.push_back(s);
+    }
+    b->active.clear();
+}
+
 // enqueue one chunk of a bucket
 int launch_chunk(fdw_server *sv, Bucket *b) {
     const int n = (int)b->active.size();
@@ -453,7 +472,12 @@ int launch_chunk(fdw_server *sv, Bucket *b) {
     c.batch = b->next_batch;
     b->next_batch ^= 1;
     int st = fdw_batch_apply(b->batch[c.batch], ops.data(), n, tm.data(), tM.data(), b->stream);
-    if (st) return lib_fail(st, "server: chunk");
+    if (st == FDW_ERR_DEVICE) return lib_fail(st, "server: chunk");
+    if (st) {  // refused before any launch: these shots fail, the others go on
+        fail_running(sv, b, std::string("server: chunk refused: ") + fdw_last_error());
+        b->next_batch = c.batch;
+        return FDW_OK;
+    }
     for (int i = 0; i < n; ++i) {
         Shot *s = b->active[i];
         s->t_next = tM[i] + 1;
@@ -680,7 +704,7 @@ int fdw_server_fetch(fdw_server *sv, int64_t ticket, float *rec_host, float *fie
     if (it == sv->shots.end()) return sfail(FDW_ERR_ARG, "server_fetch: unknown ticket %lld", (long long)ticket);
     Shot *s = it->second.get();
     if (s->state == FDW_SHOT_FAILED)
-        return sfail(FDW_ERR_STATE, "server_fetch: ticket %lld failed at admission: %s", (long long)ticket,
+        return sfail(FDW_ERR_STATE, "server_fetch: ticket %lld failed: %s", (long long)ticket,
                      s->error.c_str());
     if (s->state != FDW_SHOT_DONE) return sfail(FDW_ERR_STATE, "server_fetch: ticket %lld not finished", (long long)ticket);
     if (s->released) return sfail(FDW_ERR_STATE, "server_fetch: ticket %lld was released", (long long)ticket);

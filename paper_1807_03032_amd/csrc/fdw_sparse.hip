@@ -1,6 +1,6 @@
 // Sparse-point kernels (gfx950): receiver interpolation (gather with
 // cross-lane reductions) and source injection (scatter with atomics), and the
-// halo-zeroing kernel.  Paper: arXiv 1807.03032, Section 3.3 (eq. interp,
+// halo-zeroing kernel.  Paper: arXiv 1807.03032, Section 3.2 (eq. interp,
 // Listing finject).
 #include "fdw_device.h"
 

@@ -43,7 +43,7 @@ EXPORTS = (
     "fdw_last_error", "fdw_version", "fdw_operator_set_save", "fdw_gradient_accumulate",
     "fdw_sparse_bind_precomputed", "fdw_batch_create", "fdw_batch_apply", "fdw_batch_stats", "fdw_batch_destroy",
     "fdw_server_create", "fdw_server_footprint", "fdw_server_submit", "fdw_server_progress", "fdw_server_info",
-    "fdw_server_fetch", "fdw_server_release", "fdw_server_stats", "fdw_server_destroy",
+    "fdw_server_fetch", "fdw_server_release", "fdw_server_stats", "fdw_server_destroy", "fdw_bandwidth_probe",
 )
 FDW_SHOT_QUEUED, FDW_SHOT_RUNNING, FDW_SHOT_DONE, FDW_SHOT_FAILED = 0, 1, 2, 3
 
@@ -141,6 +141,7 @@ def load(path: str = LIB_PATH):
         "fdw_server_release": (i32, [vp, i64]),
         "fdw_server_stats": (i32, [vp, ctypes.POINTER(fdw_server_stats_t)]),
         "fdw_server_destroy": (i32, [vp]),
+        "fdw_bandwidth_probe": (i32, [i32, vp, vp, vp, ctypes.c_float, i64, vp]),
         "fdw_last_error": (ctypes.c_char_p, []),
         "fdw_version": (ctypes.c_char_p, []),
     }
@@ -163,6 +164,11 @@ def fdw_last_error() -> str:
 
 def fdw_version() -> str:
     return load().fdw_version().decode()
+
+
+def fdw_bandwidth_probe(kind: int, dst: int, a: int, b: int, s: float, n: int, stream: int = 0) -> None:
+    """One launch of the copy (kind 0) or triad (kind 1) probe on device pointers."""
+    _chk(load().fdw_bandwidth_probe(kind, dst, a, b or None, s, n, stream or None))
 
 
 def fdw_stable_dt(kind: int, ndim: int, space_order: int, vmax: float, eps_max: float, hmin: float) -> float:

@@ -7,7 +7,7 @@ HIP kernels of libfdw.so (through the C ABI in fdw.py); this module only
 orchestrates operators, buffers and the order of the steps.
 
 The adjoint follows from transposing the discrete time loop (the consistency
-the paper's Section 3.3 builds in by making injection the adjoint of
+the paper's Section 3.2 builds in by making injection the adjoint of
 interpolation): with nu = (dt^2/m) D^-1 lambda (D = 1 + eta dt/2) the
 transposed recurrence is the forward leapfrog run backwards in time, driven by
 the residual traces injected at the receivers (inside the damping division),
@@ -80,6 +80,9 @@ class IsoModeling:
         self.cp = None    # checkpoints [ncp][2 slots]: levels (kK - 1, kK)
         self.hist = None  # levels t0 + 1 .. t0 + K of one segment
         self.grad = alloc(1)
+        # changes with every new m and every forward run: the checkpoints (and
+        # q) a gradient uses belong to the state of that number
+        self.state_id = 0
 
     # ------------------------------------------------------------------ data
     def stream(self):
@@ -89,6 +92,7 @@ class IsoModeling:
         """m: logical squared slowness, numpy (nz, [ny,] nx) or a tensor of that shape."""
         t = self.torch.as_tensor(m, dtype=self.torch.float32, device=self.dev)
         fdw.slot_view(self.m, self.lay, 0).copy_(t)
+        self.state_id += 1
 
     def _slot(self, buf, k):
         return buf[k * self.E:(k + 1) * self.E]
@@ -100,6 +104,7 @@ class IsoModeling:
     def forward(self, q, checkpoints: bool = True):
         """Receiver traces [nt][nrec] of the sources q [nt][nsrc] from zero initial levels."""
         torch = self.torch
+        self.state_id += 1
         self.q.copy_(torch.as_tensor(q, dtype=torch.float32, device=self.dev).reshape(self.nt, self.nsrc))
         self.u.zero_()
         self.rec.zero_()
@@ -196,11 +201,19 @@ def wave_forward_function():
             model.set_m(m)
             traces = model.forward(q, checkpoints=True)
             ctx.model = model
+            ctx.state_id = model.state_id
+            ctx.save_for_backward(m.detach().clone(), q.detach().clone())
             return traces
 
         @staticmethod
         def backward(ctx, grad_traces):
             model = ctx.model
+            m, q = ctx.saved_tensors
+            if model.state_id != ctx.state_id:
+                # another forward (or a new m) ran on this model since: restore
+                # this call's m and recompute its checkpoints
+                model.set_m(m)
+                model.forward(q, checkpoints=True)
             g = model.gradient(grad_traces)
             gq = model.adjoint(grad_traces) if ctx.needs_input_grad[1] else None
             return g, gq, None

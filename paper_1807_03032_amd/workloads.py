@@ -212,7 +212,8 @@ def config_3d_tti_512(nt: Optional[int] = None, n: int = 512) -> Problem:
 
 def small_problem(kind: str, shape, so: int, nt: int, seed: int = 0, nsrc: int = 1, nrec: int = 16,
                   nbl: int = 4, h: float = 10.0, vrange=(1500.0, 3000.0), src_at=None,
-                  rec_coords=None, f0: Optional[float] = None, sigma_pts: float = 4.0) -> Problem:
+                  rec_coords=None, f0: Optional[float] = None, sigma_pts: float = 4.0,
+                  angle_range=(0.0, math.pi / 4)) -> Problem:
     """A small seeded problem of any shape for parity tests: smooth random models,
     sources and receivers at random positions anywhere in the grid (edges
     included), a Ricker wavelet per source with jittered delay."""
@@ -220,7 +221,7 @@ def small_problem(kind: str, shape, so: int, nt: int, seed: int = 0, nsrc: int =
     ndim = len(shape)
     extent = tuple(h * (k - 1) for k in shape)
     v = smooth_field(shape, seed + 100, vrange[0], vrange[1], sigma_pts=sigma_pts)
-    fields, eps_max = _physical_models(kind, shape, v, seed + 100, sigma_pts=sigma_pts)
+    fields, eps_max = _physical_models(kind, shape, v, seed + 100, sigma_pts=sigma_pts, angle_range=angle_range)
     vmax = float(vrange[1])
     v_eff = vmax * math.sqrt(1.0 + 2.0 * 0.3) if kind == "tti" else vmax
     dt = cfl_dt(h, v_eff, ndim)

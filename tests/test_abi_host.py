@@ -230,3 +230,13 @@ def test_server_footprint_validation():
     d.kind, d.space_order = fdw.FDW_ISO, 7
     assert fdw.load().fdw_server_footprint(ctypes.byref(d), ctypes.byref(out)) == fdw.FDW_ERR_ARG
     assert "space order" in fdw.fdw_last_error() or "space_order" in fdw.fdw_last_error()
+
+
+def test_bandwidth_probe_validation(lib):
+    """Argument checks happen before any device call (no GPU needed)."""
+    for args in ((2, 64, 64, 64, 16), (0, 0, 64, 64, 16), (1, 64, 64, 0, 16), (0, 64, 64, 64, 6),
+                 (0, 68, 64, 64, 16), (1, 64, 64, 72, 16)):
+        kind, dst, a, b, n = args
+        with pytest.raises(fdw.FdwError) as e:
+            fdw.fdw_bandwidth_probe(kind, dst, a, b, 1.0, n)
+        assert e.value.code == fdw.FDW_ERR_ARG, args

@@ -114,6 +114,34 @@ def test_tti_small(torch_dev, shape, so):
     check(prob, gf, gtr, of, otr)
 
 
+@pytest.mark.parametrize("so", [8, 12, 16])
+def test_tti_multitile_full_grid(torch_dev, so):
+    """150 x 70 x 90, 30 steps, every element compared: three 64-wide x-tiles,
+    several y-tiles of both stages and several z-chunks, so the halo exchange
+    between x-tiles, y-tiles and chunks of stage 1 and stage 2 is checked
+    everywhere, not on samples."""
+    prob = W.small_problem("tti", (150, 70, 90), so, nt=30, seed=300 + so, nsrc=2, nrec=40, nbl=6)
+    say("tti multi-tile", prob.shape, so)
+    gf, gtr, desc = gpu_run(prob, torch_dev)
+    assert "tti3d_stream" in desc, desc
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+
+
+@pytest.mark.parametrize("shape", [(150, 70, 90), (91, 77)])
+def test_tti_angles_full_turn(torch_dev, shape):
+    """theta and phi drawn over [0, 2 pi): every sign of every component of
+    the symmetry axis, through the hardware sine and cosine."""
+    prob = W.small_problem("tti", shape, 12, nt=30, seed=321, nsrc=1, nrec=30, nbl=6,
+                           angle_range=(0.0, 2.0 * np.pi))
+    th = prob.fields["theta"]
+    assert th.min() < 0.5 and th.max() > 5.5, (th.min(), th.max())
+    say("tti full-turn angles", shape)
+    gf, gtr, desc = gpu_run(prob, torch_dev)
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+
+
 @pytest.mark.parametrize("kind", ["iso", "tti"])
 def test_many_colliding_sources(torch_dev, kind):
     """More sources than the fused path holds (atomic injection), several in one cell."""
@@ -427,16 +455,10 @@ def test_tti_parameters_read_at_each_apply(torch_dev):
         np.testing.assert_array_equal(tr, rtr)
 
 
-def test_wide_fields_at_real_size(torch_dev):
-    """A grid whose padded fields pass 4 GiB (1056 x 1040 x 1040, so = 8:
-    4.9 GB per field) takes the raw-buffer form of the isotropic step.  With a
-    constant model, a source on a node in the middle and no damping layer, 10
-    steps reach 40 points from the source, so the block around it must equal,
-    bit for bit, the same block of a 101^3 run around the same source (whose
-    boundary lies beyond the reach), and match the oracle's 101^3 run."""
-    import torch
-
-    from paper_1807_03032_amd import fdw
+def wide_problems():
+    """(101^3 run, 1056 x 1040 x 1040 run) around the same source on a node:
+    constant model, no damping layer, so = 8, 10 steps, receivers within 40
+    points of the source."""
     h, so, nt, v = 10.0, 8, 10, 2000.0
     dt = W.cfl_dt(h, v, 3)
     src = W.f32(W.ricker(15.0, 1.0 / 15.0, dt, nt)).reshape(nt, 1)
@@ -448,8 +470,21 @@ def test_wide_fields_at_real_size(torch_dev):
         return W.Problem(f"wide_{shape[0]}", "iso", shape, tuple(h * (k - 1) for k in shape), (0.0,) * 3, so, 0, nt,
                          dt, v, 0.0, {"m": m}, c.reshape(1, 3), src, c + offs)
 
-    small = problem((101, 101, 101), (50, 50, 50))
-    big = problem((1056, 1040, 1040), (528, 520, 520))
+    return problem((101, 101, 101), (50, 50, 50)), problem((1056, 1040, 1040), (528, 520, 520))
+
+
+def test_wide_fields_at_real_size(torch_dev):
+    """A grid whose padded fields pass 4 GiB (1056 x 1040 x 1040, so = 8:
+    4.9 GB per field) takes the raw-buffer form of the isotropic step.  With a
+    constant model, a source on a node in the middle and no damping layer, 10
+    steps reach 40 points from the source, so the block around it must equal,
+    bit for bit, the same block of a 101^3 run around the same source (whose
+    boundary lies beyond the reach), and match the oracle's 101^3 run."""
+    import torch
+
+    from paper_1807_03032_amd import fdw
+    small, big = wide_problems()
+    so, nt = big.so, big.nt
     g = fdw.fdw_grid_create(big.shape, big.extent)
     lay = fdw.fdw_field_layout(g, so)
     fdw.fdw_grid_destroy(g)

@@ -258,3 +258,22 @@ def test_server_large_shots_run_alone(torch_dev):
     alone = serve_all([reqs[2]])[0][0]
     np.testing.assert_array_equal(out[2][0], alone[0])
     np.testing.assert_array_equal(out[2][1], alone[1])
+
+
+
+def test_server_wide_isotropic_shot(torch_dev):
+    """A served isotropic request whose padded fields pass 4 GiB (1056 x 1040
+    x 1040) gets a bucket of its own and runs the raw-buffer single-shot form:
+    its traces equal, bit for bit, those of a plain 101^3 solve around the
+    same source (the wave reaches no boundary in 10 steps); a small request
+    served beside it equals its alone-served self."""
+    from test_gpu_parity import wide_problems
+    small, big = wide_problems()
+    other = W.serve_problem("iso", 2, 201, 8, 30, seed=93, nbl=10)
+    say("served wide shot", big.shape)
+    tr_small, _ = run_alone(small, torch_dev)
+    out, stats = serve_all([big, other], keep_field=False)
+    assert stats["completed"] == 2, stats
+    np.testing.assert_array_equal(out[0][0], tr_small)
+    alone = serve_all([other], keep_field=False)[0][0]
+    np.testing.assert_array_equal(out[1][0], alone[0])

@@ -1,6 +1,6 @@
-"""GPU parity of precomputed sparse functions (Section 3.3: custom
+"""GPU parity of precomputed sparse functions (Section 3.2: custom
 interpolation given as grid points and coefficients) and of subsampled level
-saving (Section 3.5, ConditionalDimension with a factor, Listing fd-4), through
+saving (Section 3.4, ConditionalDimension with a factor, Listing fd-4), through
 the C ABI, against the FP64 oracle on identical seeded inputs.
 
 Bar: relative L2 <= 1e-4 per output (FP32 against FP64), as for the other

@@ -381,6 +381,36 @@ def test_tti_matches_dense_brute_force(ndim, so, periodic):
         np.testing.assert_allclose(a, b, atol=1e-11 * max(1.0, np.abs(b).max()))
 
 
+@pytest.mark.parametrize("ndim,so,periodic", [(2, 4, False), (2, 12, True), (3, 8, False), (3, 16, True)])
+def test_rotated_h_matches_dense_brute_force(ndim, so, periodic):
+    """H u = sum_a n_a D_a (sum_b n_b D_b u) against the dense product G G of
+    explicit first-derivative matrices, with theta and phi over a full turn
+    (every sign of every component of n)."""
+    shape = (11, 9, 10)[:ndim]
+    h = (10.0, 12.5, 8.0)[:ndim]
+    ash = tuple(reversed(shape))
+    rng = np.random.default_rng(70 + so + ndim)
+    theta = rng.uniform(0, 2 * math.pi, size=ash)
+    phi = rng.uniform(0, 2 * math.pi, size=ash) if ndim == 3 else None
+    u = rng.standard_normal(ash)
+    ext = tuple(hh * (k - 1) for hh, k in zip(h, shape))
+    g = oracle.Grid(shape, ext, so=so, periodic=periodic)
+    out = oracle.rotated_h(g, theta, phi, u)
+    R = so // 2
+    D = [brute.deriv1(shape, h, R, a, periodic) for a in range(ndim)]
+    th = theta.reshape(-1)
+    if ndim == 3:
+        ph = phi.reshape(-1)
+        n = [np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)]
+    else:
+        n = [np.sin(th), np.cos(th)]
+    G = sum(np.diag(n[a]) @ D[a] for a in range(ndim))
+    ref = (G @ (G @ u.reshape(-1))).reshape(ash)
+    np.testing.assert_allclose(out, ref, atol=1e-12 * np.abs(ref).max())
+    # a transposed operand (G^T G) or a dropped normal component would differ
+    assert np.abs((G.T @ (G @ u.reshape(-1))).reshape(ash) - ref).max() > 1e-3 * np.abs(ref).max()
+
+
 # ------------------------------------------------------------------- TTI
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_tti_reduces_to_iso(ndim):

@@ -1,4 +1,4 @@
-"""Pins of the oracle's precomputed sparse points (Section 3.3: a custom
+"""Pins of the oracle's precomputed sparse points (Section 3.2: a custom
 interpolation scheme given as grid points and coefficients per sparse point,
 behaving like a sparse function with linear weights).
 
