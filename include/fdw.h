@@ -213,6 +213,21 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out);
  * Errors: FDW_ERR_ARG (range), FDW_ERR_DEVICE. */
 int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream);
 
+/* Allocation-free variant of fdw_operator_apply, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same time loop and kernels, with the
+ * TTI gradient buffers (2 * elems_per_slot floats, the only scratch the
+ * kernels use) taken from a library-owned device array of 64 MiB per GPU
+ * instead of the operator's own buffers; the isotropic operator uses no
+ * scratch.  It calls no allocating routine and creates no events (kernel
+ * timing is not recorded).  The scratch region is cleared on `stream` at the
+ * start of each call.  Every call on one GPU shares that GPU's array: calls
+ * whose work overlaps on one GPU (several streams, or concurrent host threads)
+ * race and must be serialised by the caller.
+ * Errors: FDW_ERR_ARG (range; an operator whose gradient buffers exceed the
+ * 64 MiB scratch: 3D TTI grids up to about 180^3 fit), FDW_ERR_DEVICE. */
+int fdw_operator_apply_noalloc(fdw_op *op, int time_m, int time_M, void *stream);
+
 /* Subsampled level saving (Section 3.4, ConditionalDimension / save=): while
  * the isotropic operator runs, every level L >= first_level with
  * (L - first_level) % every == 0 and k = (L - first_level) / every < nlevels

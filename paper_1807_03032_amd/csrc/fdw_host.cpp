@@ -847,7 +847,7 @@ static void iso_step_args(const fdw_op *op, int t, IsoArgs &a) {
     a.rec = nullptr;
 }
 
-static void tti_step_args(const fdw_op *op, int t, TtiArgs &a) {
+static void tti_step_args(const fdw_op *op, int t, TtiArgs &a, float *stage) {
     const fdw_op_desc &d = op->d;
     const int64_t E = op->lay.elems_per_slot;
     const int S = d.u->nslots;
@@ -865,8 +865,8 @@ static void tti_step_args(const fdw_op *op, int t, TtiArgs &a) {
     a.delta = d.delta->d;
     a.theta = d.theta->d;
     a.phi = d.phi ? d.phi->d : nullptr;
-    a.gp = op->d_stage;
-    a.gr = op->d_stage + E;
+    a.gp = stage;
+    a.gr = stage + E;
     a.eta_x = op->d_eta;
     a.eta_y = op->d_eta + op->geom.nx;
     a.eta_z = op->d_eta + op->geom.nx + op->geom.ny;
@@ -949,8 +949,9 @@ static int timing_close(fdw_op *op, hipStream_t s) {
     return FDW_OK;
 }
 
-int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
-    FDW_GUARD_BEGIN
+// The apply loop.  stage: the TTI gradient buffers (gp | gr, elems_per_slot
+// each); timed: the operator's kernel timing (which creates events) applies.
+static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *stage, bool timed) {
     if (!op) return fail(FDW_ERR_ARG, "operator_apply: NULL op");
     const fdw_op_desc &d = op->d;
     hipStream_t s = (hipStream_t)stream;
@@ -972,7 +973,8 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
     const float *eta_x = op->d_eta, *eta_z = op->d_eta + op->geom.nx + op->geom.ny;
     const int nsrc = d.src ? d.src->npoint : 0;
     const int nrec = d.rec ? d.rec->npoint : 0;
-    if (op->timing) op->last_stream = s;
+    timed = timed && op->timing;
+    if (timed) op->last_stream = s;
 
     SparseArgs inj = sparse_template(op, d.src, false);
     SparseArgs itp = sparse_template(op, d.rec, true);
@@ -982,11 +984,11 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         Persist2DArgs pa;
         persist2d_args(op, time_m, time_M, pa);
         LaunchEvents ev;
-        int st = timing_next(op, ev);
+        int st = (timed ? timing_next(op, ev) : FDW_OK);
         if (st) return st;
         hipError_t e = launch_iso2d_persistent(op->R, pa, s, ev);
         if (e != hipSuccess) return fail_hip(e, "operator_apply: persistent 2D launch");
-        return timing_close(op, s);
+        return timed ? timing_close(op, s) : FDW_OK;
     }
     // 2D temporal blocking: passes of up to K steps, each reading its two input
     // levels from one pair of buffers and writing its two output levels to the
@@ -1029,12 +1031,12 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
                 a.rec_rows = d.rec->data + (int64_t)t0 * nrec;
             }
             LaunchEvents ev;
-            if (int st = timing_next(op, ev)) return st;
+            if (int st = (timed ? timing_next(op, ev) : FDW_OK)) return st;
             hipError_t e = launch_iso2d_tb(op->R, a, s, ev);
             if (e != hipSuccess) return fail_hip(e, "operator_apply: temporal-blocking launch");
             std::swap(X, Y);
         }
-        return timing_close(op, s);
+        return timed ? timing_close(op, s) : FDW_OK;
     }
     const int S_ring = d.u->nslots + 1;
     // the 3D streaming kernels sample the receivers of step t - 1 inside the
@@ -1058,7 +1060,7 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         }
         const int sn = (t + 1) % d.u->nslots;
         LaunchEvents ev;
-        if (int st = timing_next(op, ev)) return st;
+        if (int st = (timed ? timing_next(op, ev) : FDW_OK)) return st;
         hipError_t e;
         float *next_field;
         float *save_dst = nullptr;
@@ -1082,7 +1084,7 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             next_field = a.u_next;
         } else {
             TtiArgs a;
-            tti_step_args(op, t, a);
+            tti_step_args(op, t, a, stage);
             SparseArgs prev_itp = itp;
             a.rec = nullptr;
             if (fuse_interp && t > time_m) {
@@ -1122,7 +1124,7 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
             }
         }
     }
-    if (int st = timing_close(op, s)) return st;
+    if (int st = timed ? timing_close(op, s) : FDW_OK) return st;
     // the caller's stream covers every receiver sample of this apply
     if (op->overlap_interp && nrec > 0 && time_M >= time_m) {
         const int last = std::max(time_m, time_M - d.u->nslots + 1);
@@ -1132,6 +1134,13 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
         }
     }
     return FDW_OK;
+}
+
+
+int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
+    FDW_GUARD_BEGIN
+    if (!op) return fail(FDW_ERR_ARG, "operator_apply: NULL op");
+    return apply_impl(op, time_m, time_M, stream, op->d_stage, true);
     FDW_GUARD_END
 }
 
@@ -1245,6 +1254,17 @@ int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_b
 }
 
 }  // extern "C"
+
+int64_t fdw::operator_stage_floats(const fdw_op *op) {
+    return op && op->d.kind == FDW_TTI ? 2 * op->lay.elems_per_slot : 0;
+}
+
+int fdw::operator_apply_stage(fdw_op *op, int time_m, int time_M, void *stream, float *stage) {
+    FDW_GUARD_BEGIN
+    if (!op) return fail(FDW_ERR_ARG, "operator_apply: NULL op");
+    return apply_impl(op, time_m, time_M, stream, stage, false);
+    FDW_GUARD_END
+}
 
 // ---------------------------------------------------------------------------
 // Fused multi-shot steps: several operators of one geometry advance together,
@@ -1450,7 +1470,7 @@ int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, 
                 multi_pack_iso(ndim, a, live, ndim == 3 ? rec : none, base + r1 * i);
             } else {
                 TtiArgs a;
-                tti_step_args(op, t, a);
+                tti_step_args(op, t, a, op->d_stage);
                 multi_pack_tti(ndim, a, live, ndim == 3 ? rec : none, base + r1 * i, r2 ? base + off2 + r2 * i : nullptr);
             }
             if (ndim == 2) std::memcpy(base + offs + rs * i, &rec, sizeof(rec));

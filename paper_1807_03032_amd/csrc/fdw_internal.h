@@ -221,6 +221,17 @@ hipError_t launch_gradient(int ndim, const GradArgs &a, hipStream_t s);
 hipError_t launch_zero_halo(int ndim, const Geom &g, int R, int64_t pitch_x, int64_t pitch_y,
                             int64_t planes, float *base, hipStream_t s);
 
+}  // namespace fdw
+struct fdw_op;
+namespace fdw {
+// Floats of TTI gradient buffers an operator's apply needs (2 slots; 0 for
+// the isotropic operator), and the apply loop with those buffers at `stage`
+// instead of the operator's own, without kernel timing (no event creation).
+int64_t operator_stage_floats(const fdw_op *op);
+int operator_apply_stage(fdw_op *op, int time_m, int time_M, void *stream, float *stage);
+// zero n floats (a fill kernel: no memset node when the stream is captured)
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
+
 // Bandwidth probes: kind 0 copies dst = a, kind 1 is the triad dst = a + s b
 // (n floats, a multiple of 4, 16-byte aligned pointers).
 hipError_t launch_bandwidth_probe(int kind, float *dst, const float *a, const float *b, float s, int64_t n,

@@ -4,6 +4,8 @@
 // the STREAM triad rate as the attainable peak of its roofline plots).
 #include "fdw_internal.h"
 
+#include <algorithm>
+
 namespace fdw {
 
 // Each workgroup moves a contiguous block of kProbeVec float4 per thread,
@@ -51,6 +53,17 @@ hipError_t launch_bandwidth_probe(int kind, float *dst, const float *a, const fl
     else
         hipLaunchKernelGGL(bandwidth_probe<1>, dim3((unsigned)blocks), dim3(kProbeThreads), 0, st, (float4 *)dst,
                            (const float4 *)a, (const float4 *)b, s, n4);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) fill_zero_kernel(float *__restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.0f;
+}
+
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

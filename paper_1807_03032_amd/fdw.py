@@ -44,6 +44,7 @@ EXPORTS = (
     "fdw_sparse_bind_precomputed", "fdw_batch_create", "fdw_batch_apply", "fdw_batch_stats", "fdw_batch_destroy",
     "fdw_server_create", "fdw_server_footprint", "fdw_server_submit", "fdw_server_progress", "fdw_server_info",
     "fdw_server_fetch", "fdw_server_release", "fdw_server_stats", "fdw_server_destroy", "fdw_bandwidth_probe",
+    "fdw_operator_apply_noalloc",
 )
 FDW_SHOT_QUEUED, FDW_SHOT_RUNNING, FDW_SHOT_DONE, FDW_SHOT_FAILED = 0, 1, 2, 3
 
@@ -120,6 +121,7 @@ def load(path: str = LIB_PATH):
         "fdw_sparse_destroy": (i32, [vp]),
         "fdw_operator_create": (i32, [ctypes.POINTER(fdw_op_desc), pvp]),
         "fdw_operator_apply": (i32, [vp, i32, i32, vp]),
+        "fdw_operator_apply_noalloc": (i32, [vp, i32, i32, vp]),
         "fdw_sync": (i32, [vp]),
         "fdw_operator_destroy": (i32, [vp]),
         "fdw_operator_set_timing": (i32, [vp, i32]),
@@ -256,6 +258,10 @@ def fdw_operator_create(desc: fdw_op_desc) -> int:
 
 def fdw_operator_apply(op, time_m: int, time_M: int, stream: Optional[int] = None):
     _chk(load().fdw_operator_apply(op, time_m, time_M, stream))
+
+
+def fdw_operator_apply_noalloc(op, time_m: int, time_M: int, stream: Optional[int] = None):
+    _chk(load().fdw_operator_apply_noalloc(op, time_m, time_M, stream))
 
 
 def fdw_sync(op):
