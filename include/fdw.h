@@ -229,13 +229,16 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream);
 int fdw_operator_apply_noalloc(fdw_op *op, int time_m, int time_M, void *stream);
 
 /* Subsampled level saving (Section 3.4, ConditionalDimension / save=): while
- * the isotropic operator runs, every level L >= first_level with
+ * the operator runs, every level L >= first_level with
  * (L - first_level) % every == 0 and k = (L - first_level) / every < nlevels
- * is also stored in buf + k * elems_per_slot (same layout; halos untouched).
- * Level L is the one step L - 1 computes (after injection); the initial level
- * 0 (slot 0) is stored when an apply starts at time_m = 0.  buf = NULL
- * disables saving.  The store is fused into the stencil kernel when the sources
- * are fused.  Errors: FDW_ERR_ARG (TTI operator, every < 1, nlevels < 0). */
+ * is also stored in the buffer (same layout; halos untouched): the isotropic
+ * operator stores u at buf + k * elems_per_slot, the TTI operator p at
+ * buf + 2k * elems_per_slot and r at buf + (2k + 1) * elems_per_slot (buf
+ * holds 2 * nlevels slots).  Level L is the one step L - 1 computes (after
+ * injection); the initial level 0 (slot 0) is stored when an apply starts at
+ * time_m = 0.  buf = NULL disables saving.  The store is fused into the
+ * stencil kernel (TTI: stage 2) when the sources are fused.
+ * Errors: FDW_ERR_ARG (every < 1, nlevels < 0). */
 int fdw_operator_set_save(fdw_op *op, float *buf, int64_t nlevels, int every, int first_level);
 
 /* Adjoint-state gradient with respect to m (zero-lag imaging condition of the

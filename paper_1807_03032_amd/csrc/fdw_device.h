@@ -34,14 +34,39 @@ __device__ __forceinline__ void lds_barrier() {
 
 // Leapfrog update with the damping term (centred first time derivative):
 //   u+ = [2u - (1 - a) u- + c L] / (1 + a),   a = eta dt / 2,  c = dt^2 / m.
-// In the undamped interior a = 0 and no division is needed.
 // Written as u + increment, with d = u - u-:
-//   u+ = u + [(1 - a) d + c L] / (1 + a),
-// which rounds once at the scale of u instead of twice.
+//   u+ = u + [(1 - a) d + c L] * (1 / (1 + a)),
+// which rounds once at the scale of u instead of twice.  The division is a
+// hardware reciprocal (1 ulp) and a product: no branch, and in the undamped
+// interior (a = 0) every step is exact, so the result there is u + (d + c L)
+// bit for bit.
+// The multiply-adds of the point updates are written out (fmaf) and nothing
+// else is fused (contract off), so every kernel that inlines them rounds the
+// same way whatever code surrounds them.
 __device__ __forceinline__ float leapfrog(float u, float u_prev, float cl, float a) {
+#pragma clang fp contract(off)
     const float d = u - u_prev;
-    if (a == 0.0f) return u + (d + cl);
-    return u + ((1.0f - a) * d + cl) / (1.0f + a);
+    return __builtin_fmaf(__builtin_fmaf(1.0f - a, d, cl), __builtin_amdgcn_rcpf(1.0f + a), u);
+}
+
+// One pair term of the difference-form Laplacian: acc + w ((a + b) - 2u).
+__device__ __forceinline__ float lap_term(float acc, float w, float a, float b, float u) {
+#pragma clang fp contract(off)
+    return __builtin_fmaf(w, __builtin_fmaf(-2.0f, u, a + b), acc);
+}
+
+// One term of a centred first derivative: acc + w (a - b).
+__device__ __forceinline__ float d1_term(float acc, float w, float a, float b) {
+#pragma clang fp contract(off)
+    return __builtin_fmaf(w, a - b, acc);
+}
+
+// n . (dx, dy, dz) with the same roundings everywhere: x first, z last, so
+// that for the small tilts of the workloads the dominant z term enters the
+// last multiply-add unrounded.
+__device__ __forceinline__ float dot3(float nx, float dx, float ny, float dy, float nz, float dz) {
+#pragma clang fp contract(off)
+    return __builtin_fmaf(nz, dz, __builtin_fmaf(ny, dy, nx * dx));
 }
 
 // Laplacian at element i as sum over axes and k of w_k ((u(+k) + u(-k)) - 2u).
@@ -49,13 +74,13 @@ __device__ __forceinline__ float leapfrog(float u, float u_prev, float cl, float
 // zero on constants after the weights are rounded to float.
 template <int NDIM, int R>
 __device__ __forceinline__ float laplacian_at(const float *u, int64_t i, const Geom &g, const Coefs &c) {
-    const float u2 = 2.0f * u[i];
+    const float uc = u[i];
     float lap = 0.0f;
 #pragma unroll
     for (int k = 1; k <= R; ++k) {
-        lap += c.w2[0][k] * ((u[i + k] + u[i - k]) - u2);
-        lap += c.w2[2][k] * ((u[i + k * g.sz] + u[i - k * g.sz]) - u2);
-        if (NDIM == 3) lap += c.w2[1][k] * ((u[i + k * g.sy] + u[i - k * g.sy]) - u2);
+        lap = lap_term(lap, c.w2[0][k], u[i + k], u[i - k], uc);
+        lap = lap_term(lap, c.w2[2][k], u[i + k * g.sz], u[i - k * g.sz], uc);
+        if (NDIM == 3) lap = lap_term(lap, c.w2[1][k], u[i + k * g.sy], u[i - k * g.sy], uc);
     }
     return lap;
 }

@@ -112,7 +112,9 @@ struct fdw_op {
     TtiVariant tti_v = TtiVariant::Naive;
     bool use_persist2d = false;  // 2D iso grid small enough for the LDS-resident kernel
     bool use_tb2d = false;       // 2D iso: K steps per launch on overlapped LDS patches
+    bool use_tb3d = false;       // 3D iso: two steps per launch
     float *d_tb = nullptr;       // temporal blocking: second pair of level buffers
+    FusedSrc *d_fsrc = nullptr;  // device copy of the fused sources (3D temporal blocking)
     // library-owned device memory
     float *d_eta = nullptr;           // eta_x | eta_y | eta_z (times dt/2)
     float *d_stage = nullptr;         // TTI: gp | gr (each elems_per_slot)
@@ -458,6 +460,8 @@ int fdw_sparse_destroy(fdw_sparse *s) {
 static void release_device(fdw_op *op) {
     if (op->d_eta) (void)hipFree(op->d_eta);
     if (op->d_stage) (void)hipFree(op->d_stage);
+    if (op->d_fsrc) (void)hipFree(op->d_fsrc);
+    op->d_fsrc = nullptr;
     if (op->d_tb) (void)hipFree(op->d_tb);
     op->d_tb = nullptr;
     if (op->d_src_base) (void)hipFree(op->d_src_base);
@@ -678,6 +682,10 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
                 for (int c = 0; c < (1 << g->ndim); ++c)
                     F.w[s][c] = (float)(d.dt * d.dt * d.src->w[(size_t)s * (1 << g->ndim) + c]);
             }
+            // the temporal-blocking kernel reads the record from device memory
+            e = hipMalloc((void **)&op->d_fsrc, sizeof(FusedSrc));
+            if (e == hipSuccess) e = hipMemcpy(op->d_fsrc, &F, sizeof(FusedSrc), hipMemcpyHostToDevice);
+            if (e != hipSuccess) st = fail(FDW_ERR_NOMEM, "operator_create: fused sources: %s", hipGetErrorString(e));
         }
     }
     if (!st && d.rec) st = upload_sparse(op, d.rec, 1.0, &op->d_rec_base, &op->d_rec_w, &op->d_rec_idx);
@@ -736,6 +744,27 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
                 release_device(op);
                 delete op;
                 return fail(FDW_ERR_NOMEM, "operator_create: level buffers: %s", hipGetErrorString(e2));
+            }
+        }
+    }
+    // 3D isotropic grids advance two steps per launch (temporal blocking,
+    // FDW_TB3D=1; 0 keeps one launch per step); in-place two-slot storage,
+    // fused (or no) sources, linear (or no) receivers, fields below 2 GiB
+    {
+        const char *tb = std::getenv("FDW_TB3D");
+        const bool on = tb && tb[0] == '1';
+        const bool small_fields = (L.elems_per_slot * (int64_t)sizeof(float)) < ((int64_t)1 << 31);
+        op->use_tb3d = on && d.kind == FDW_ISO && op->ndim == 3 && d.mode == FDW_FORWARD &&
+                       op->iso_v == IsoVariant::Stream && small_fields && d.u->nslots == 2 &&
+                       (!d.src || d.src->npoint == 0 || op->src_fused) && (!d.rec || d.rec->npoint == 0 || d.rec->r == 2);
+        if (op->use_tb3d) {
+            const size_t bytes = sizeof(float) * (size_t)L.elems_per_slot * 2;
+            hipError_t e2 = hipMalloc((void **)&op->d_tb, bytes);
+            if (e2 == hipSuccess) e2 = hipMemset(op->d_tb, 0, bytes);
+            if (e2 != hipSuccess) {
+                release_device(op);
+                delete op;
+                return fail(FDW_ERR_NOMEM, "operator_create: temporal-blocking buffers: %s", hipGetErrorString(e2));
             }
         }
     }
@@ -1038,17 +1067,81 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
         }
         return timed ? timing_close(op, s) : FDW_OK;
     }
+    // 3D temporal blocking: pairs of steps, each pass reading levels t - 1, t
+    // from one buffer pair and writing t + 1, t + 2 to the other, the pass
+    // count fixing which pair the first pass reads so that the last writes
+    // the TimeFunction's slots; receivers of a pass are sampled inside the
+    // next pass, those of the last pass by their own launches; an odd last
+    // step runs the per-step kernel below
+    if (op->use_tb3d && !op->save_buf && time_M - time_m + 1 >= 2) {
+        const int P = (time_M - time_m + 1) / 2;
+        float *A = d.u->d, *B = op->d_tb;
+        if (P % 2 == 1) {
+            hipError_t e = hipMemcpyAsync(op->d_tb, d.u->d, sizeof(float) * 2 * (size_t)E, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return fail_hip(e, "operator_apply: level copy");
+            std::swap(A, B);
+        }
+        for (int k = 0; k < P; ++k) {
+            const int t = time_m + 2 * k;
+            TB3DArgs a{};
+            a.f.g = op->geom;
+            a.f.in_prev = A + (int64_t)((t + 1) % 2) * E;  // level t - 1
+            a.f.in_cur = A + (int64_t)(t % 2) * E;
+            a.f.out_prev = B + (int64_t)((t + 1) % 2) * E;  // level t + 1
+            a.f.out_cur = B + (int64_t)(t % 2) * E;         // level t + 2
+            a.f.m = d.m->d;
+            a.f.eta_x = op->d_eta;
+            a.f.eta_y = op->d_eta + op->geom.nx;
+            a.f.eta_z = eta_z;
+            a.f.dt2 = op->dt2;
+            a.c = op->coefs;
+            a.fsrc = op->src_fused && nsrc > 0 ? op->d_fsrc : nullptr;
+            if (nsrc > 0) {
+                a.q1 = d.src->data + (int64_t)t * nsrc;
+                a.q2 = d.src->data + (int64_t)(t + 1) * nsrc;
+            }
+            if (nrec > 0 && t > time_m) {  // rows t - 2, t - 1 from levels t - 1, t
+                a.rec[0] = itp;
+                a.rec[0].field = const_cast<float *>(a.f.in_prev);
+                a.rec[0].rec_row = d.rec->data + (int64_t)(t - 2) * nrec;
+                a.rec[1] = itp;
+                a.rec[1].field = const_cast<float *>(a.f.in_cur);
+                a.rec[1].rec_row = d.rec->data + (int64_t)(t - 1) * nrec;
+            }
+            LaunchEvents ev;
+            if (int st = (timed ? timing_next(op, ev) : FDW_OK)) return st;
+            hipError_t e = launch_iso3d_tb2(op->R, a, s, ev);
+            if (e != hipSuccess) return fail_hip(e, "operator_apply: temporal-blocking launch");
+            std::swap(A, B);
+        }
+        const int tl = time_m + 2 * P - 2;  // the last pass computed levels tl + 1, tl + 2
+        if (nrec > 0) {
+            for (int r = 0; r < 2; ++r) {
+                itp.field = d.u->d + (int64_t)((tl + 1 + r) % 2) * E;
+                itp.rec_row = d.rec->data + (int64_t)(tl + r) * nrec;
+                hipError_t e = launch_interp(itp, s);
+                if (e != hipSuccess) return fail_hip(e, "operator_apply: interp launch");
+            }
+        }
+        time_m += 2 * P;
+        if (time_m > time_M) return timed ? timing_close(op, s) : FDW_OK;
+    }
     const int S_ring = d.u->nslots + 1;
     // the 3D streaming kernels sample the receivers of step t - 1 inside the
     // launch of step t (extra workgroups reading level t); the last step of the
     // apply is sampled by its own launch after the loop
     const bool fuse_interp = nrec > 0 && op->ndim == 3 && !op->overlap_interp && interp_lanes_ok(itp) &&
                              (d.kind == FDW_ISO ? op->iso_v == IsoVariant::Stream : op->tti_v == TtiVariant::Stream);
+    // saved level k occupies `fields` slots of the buffer (isotropic: u;
+    // TTI: p then r)
+    const int fields = d.kind == FDW_TTI ? 2 : 1;
     // the initial level 0 is no step's output: an apply from time 0 stores it
     if (op->save_buf && time_m == 0 && time_M >= time_m && op->save_first <= 0 && op->save_first % op->save_every == 0 &&
         -op->save_first / op->save_every < op->save_nlevels) {
-        float *dst = op->save_buf + (int64_t)(-op->save_first / op->save_every) * E;
+        float *dst = op->save_buf + (int64_t)(-op->save_first / op->save_every) * fields * E;
         hipError_t e = hipMemcpyAsync(dst, d.u->d, sizeof(float) * (size_t)E, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && d.kind == FDW_TTI)
+            e = hipMemcpyAsync(dst + E, d.r->d, sizeof(float) * (size_t)E, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return fail_hip(e, "operator_apply: save copy of level 0");
     }
     for (int t = time_m; t <= time_M; ++t) {
@@ -1064,6 +1157,12 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
         hipError_t e;
         float *next_field;
         float *save_dst = nullptr;
+        {
+            const int L = t + 1;
+            if (op->save_buf && L >= op->save_first && (L - op->save_first) % op->save_every == 0 &&
+                (L - op->save_first) / op->save_every < op->save_nlevels)
+                save_dst = op->save_buf + (int64_t)((L - op->save_first) / op->save_every) * fields * E;
+        }
         if (d.kind == FDW_ISO) {
             IsoArgs a;
             iso_step_args(op, t, a);
@@ -1074,12 +1173,7 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
                 prev_itp.rec_row = d.rec->data + (int64_t)(t - 1) * nrec;
                 a.rec = &prev_itp;
             }
-            const int L = t + 1;
-            if (op->save_buf && L >= op->save_first && (L - op->save_first) % op->save_every == 0 &&
-                (L - op->save_first) / op->save_every < op->save_nlevels) {
-                save_dst = op->save_buf + (int64_t)((L - op->save_first) / op->save_every) * E;
-                if (op->src_fused || nsrc == 0) a.save = save_dst;
-            }
+            if (save_dst && (op->src_fused || nsrc == 0)) a.save = save_dst;
             e = launch_iso(op->ndim, op->R, op->iso_v, a, s, ev);
             next_field = a.u_next;
         } else {
@@ -1091,6 +1185,10 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
                 prev_itp.field = const_cast<float *>(a.p_cur);  // level t, read-only in this launch
                 prev_itp.rec_row = d.rec->data + (int64_t)(t - 1) * nrec;
                 a.rec = &prev_itp;
+            }
+            if (save_dst && (op->src_fused || nsrc == 0)) {
+                a.save_p = save_dst;
+                a.save_r = save_dst + E;
             }
             e = launch_tti(op->ndim, op->R, op->tti_v, a, s, ev);
             next_field = a.p_next;
@@ -1107,6 +1205,8 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
         }
         if (save_dst && !(op->src_fused || nsrc == 0)) {
             e = hipMemcpyAsync(save_dst, next_field, sizeof(float) * (size_t)E, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess && d.kind == FDW_TTI)
+                e = hipMemcpyAsync(save_dst + E, d.r->d + sn * E, sizeof(float) * (size_t)E, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return fail_hip(e, "operator_apply: save copy");
         }
         if (nrec > 0 && (!fuse_interp || t == time_M)) {
@@ -1146,7 +1246,6 @@ int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
 
 int fdw_operator_set_save(fdw_op *op, float *buf, int64_t nlevels, int every, int first_level) {
     if (!op) return fail(FDW_ERR_ARG, "set_save: NULL op");
-    if (buf && op->d.kind != FDW_ISO) return fail(FDW_ERR_ARG, "set_save: level saving is available for the isotropic operator");
     if (buf && (every < 1 || nlevels < 0)) return fail(FDW_ERR_ARG, "set_save: every must be >= 1 and nlevels >= 0");
     op->save_buf = buf;
     op->save_nlevels = buf ? nlevels : 0;
@@ -1240,6 +1339,7 @@ int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_b
     }
     const char *name = iso ? (op->use_persist2d ? "iso2d_persistent (LDS-resident, one launch per apply)"
                               : op->use_tb2d    ? tbname
+                              : op->use_tb3d    ? tb3d_kernel_name(op->geom, op->R)
                                                 : iso_kernel_name(op->ndim, op->iso_v, op->geom))
                            : tti_kernel_name(op->ndim, op->tti_v, op->geom);
     snprintf(buf, (size_t)buflen, "%s so=%d R=%d ndim=%d src=%s nsrc=%d nrec=%d", name, op->d.space_order, op->R,
@@ -1248,8 +1348,9 @@ int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_b
     // algorithmic HBM bytes per point per step: iso reads u^n, u^n-1, m and
     // writes u^n+1; TTI reads p, r at two levels and m, eps, delta, theta(, phi)
     // and writes p, r.
+    // A temporal-blocking launch does two steps' work: 32 B per point.
     if (alg_bytes_per_point)
-        *alg_bytes_per_point = iso ? 16.0 : (op->ndim == 3 ? 44.0 : 40.0);
+        *alg_bytes_per_point = iso ? (op->use_tb3d ? 32.0 : 16.0) : (op->ndim == 3 ? 44.0 : 40.0);
     return FDW_OK;
 }
 

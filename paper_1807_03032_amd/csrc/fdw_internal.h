@@ -65,6 +65,7 @@ struct TtiArgs {
     float *p_next, *r_next;
     const float *m, *eps, *delta, *theta, *phi;
     float *gp, *gr;  // stage buffers: rotated gradients n . grad p, n . grad r
+    float *save_p, *save_r;  // optional: the new levels are also stored here (same layout)
     const float *eta_x, *eta_y, *eta_z;
     float dt2;
     Coefs c;
@@ -170,6 +171,32 @@ struct TB2DArgs {
     float *rec_rows;                // row of step t0 (row stride nrec)
 };
 
+// Temporal blocking of the 3D isotropic step (two steps per launch): levels
+// t - 1, t are read from one buffer pair, levels t + 1, t + 2 written to the
+// other; the sources of steps t and t + 1 are fused (their cells and weights
+// read from device memory, only by workgroups they touch); rec[0], rec[1] are
+// receiver rows sampled in the same launch from levels the launch only reads
+// (npoint = 0: none).
+struct TB3DFields {
+    Geom g;
+    const float *in_prev, *in_cur;
+    float *out_prev, *out_cur;
+    const float *m;
+    const float *eta_x, *eta_y, *eta_z;
+    float dt2;
+};
+struct TB3DArgs {
+    TB3DFields f;
+    Coefs c;
+    const FusedSrc *fsrc;     // device copy of the fused sources (n = 0: none)
+    const float *q1, *q2;     // source samples of steps t and t + 1
+    SparseArgs rec[2];
+};
+struct TB3DShape {
+    int tx, ty;  // output tile
+};
+TB3DShape tb3d_shape(int R);
+
 // steps per pass and inner tile of the 2D temporal blocking at radius R
 struct TB2DShape {
     int k, ix, iz;
@@ -190,6 +217,9 @@ enum class TtiVariant { Naive = 0, Stream = 1 };
 struct LaunchEvents {
     hipEvent_t start = nullptr, stop = nullptr;
 };
+
+hipError_t launch_iso3d_tb2(int R, const TB3DArgs &a, hipStream_t s, const LaunchEvents &ev);
+const char *tb3d_kernel_name(const Geom &g, int R);
 
 // Launchers (fdw_iso.hip, fdw_tti.hip, fdw_sparse.hip).  Each returns the
 // hipError_t of its launch.

@@ -3,6 +3,8 @@
 // Paper: arXiv 1807.03032, eq. WE and Listings fd-2/fd-3 (update), Listing
 // finject (injection), Section 7.2 (damping layer, test cases).
 #include "fdw_device.h"
+#include "fdw_iso_op.h"
+#include "fdw_stream2.h"
 
 namespace fdw {
 
@@ -45,46 +47,6 @@ __global__ void __launch_bounds__(256) iso2d_naive_multi(const NaiveShot<IsoArgs
     iso_naive_point<2, R>(S.a, x, 0, z);
 }
 
-// ---- isotropic step: stencil field u(t); pointwise u(t-1), m ----------------
-struct IsoOp {
-    static constexpr bool kBufferAccess = false;  // raw buffer (true) or global accesses
-    Coefs c;
-    DampTables eta;
-    float dt2;
-    FusedSrc src;
-    float *u_next;
-    float *save;   // optional second destination of the new level
-    int adjoint;   // injected terms divided by (1 + a)
-    // does a fused source touch this tile and chunk?
-    __device__ __forceinline__ bool begin_tile(int x0, int tx, int y0, int ty, int z0, int z1) const {
-        return src_in_tile(src, x0, tx, y0, ty, z0, z1);
-    }
-    // damping: eta_x + eta_y per column, + eta_z per plane
-    __device__ __forceinline__ float begin_column(int x, int y) const { return eta.column(x, y); }
-    __device__ __forceinline__ float begin_plane(int z) const { return eta.plane(z); }
-    template <int R, class P>
-    __device__ __forceinline__ void point(const P &pt, bool src_here, float a, bool live) const {
-        const float uc = pt.qz(0, 0);
-        const float u2 = 2.0f * uc;
-        // Laplacian as sum_k w_k ((u+k + u-k) - 2u): no centre weight, so
-        // rounding the weights cannot add a spurious mass term
-        float lap = 0.0f;
-#pragma unroll
-        for (int k = 1; k <= R; ++k) {
-            lap += c.w2[2][k] * ((pt.qz(0, k) + pt.qz(0, -k)) - u2);
-            lap += c.w2[0][k] * ((pt.qx(0, k) + pt.qx(0, -k)) - u2);
-            lap += c.w2[1][k] * ((pt.qy(0, k) + pt.qy(0, -k)) - u2);
-        }
-        const float rm = fast_rcp(pt.p(1));
-        float v = leapfrog(uc, pt.p(0), dt2 * rm * lap, a);
-        if (src_here) v = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, v, adjoint ? 1.0f / (1.0f + a) : 1.0f);
-        if (live) {
-            pt.store(u_next, v);
-            if (save) pt.store(save, v);
-        }
-    }
-};
-
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -114,6 +76,11 @@ static int iso_default_zchunk(const Geom &g) {
 
 static IsoShape iso_stream_shape(const Geom &g) {
     IsoShape sh{2, iso_default_zchunk(g), 2, 4};
+    // grids with 2048 or more 64 x 16 tile chunks of 64 planes (512^3 and up)
+    // take that shape (8 waves): half the y-halo rows and warm-up planes per
+    // point of the 64 x 8 x 32 default (512^3: 451 vs 470 us per step)
+    const int64_t cols16 = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
+    if (cols16 * ((g.nz + 63) / 64) >= 2048) sh = IsoShape{2, 64, 2, 8};
     if (const char *e = std::getenv("FDW_ISO_TILE")) {
         int a = 0, b = 0, c = 1, d = 4;
         const int n = std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d);
@@ -138,8 +105,25 @@ static bool iso_wide_form(const Geom &g) {
 }
 static StreamFields<1, 2> iso_fields(const IsoArgs &a);
 
+// engine of the 3D isotropic step: the ring-buffer engine at orders up to 8
+// (FDW_ENGINE=1 forces the shifting-queue engine), the shifting-queue engine
+// above (there the ring kernel copies its operator record to scratch memory)
+// and for the wide form
+static bool iso_ring_engine(int R) {
+    static const bool ring = [] {
+        const char *e = std::getenv("FDW_ENGINE");
+        return !(e && e[0] == '1');
+    }();
+    return ring && R <= 4;
+}
+
 template <int R, int NY, int PF, int BY>
 static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t s, const LaunchEvents &ev) {
+    if constexpr (R <= 4) {
+        if (iso_ring_engine(R))
+            return launch_stream3d_ring<R, NY, PF, BY>(make_iso_op(a), iso_fields(a), a.g, zc, s, ev.start, ev.stop,
+                                                       a.rec);
+    }
     return launch_stream3d<R, NY, PF, BY>(make_iso_op(a), iso_fields(a), a.g, zc, s, ev.start, ev.stop, a.rec);
 }
 

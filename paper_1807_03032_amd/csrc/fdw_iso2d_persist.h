@@ -67,7 +67,6 @@ __device__ __forceinline__ void iso2d_persistent_body(const Persist2DArgs &a) {
                 const int x = i % nx, z = i / nx;
                 const int l = z * lw + x;
                 const float uc = cur[l];
-                const float u2 = 2.0f * uc;
                 float lap = 0.0f;
 #pragma unroll
                 for (int k = 1; k <= R; ++k) {
@@ -75,8 +74,8 @@ __device__ __forceinline__ void iso2d_persistent_body(const Persist2DArgs &a) {
                     const float xm = (HALO || x - k >= 0) ? cur[l - k] : 0.0f;
                     const float zp = (HALO || z + k < nz) ? cur[l + k * lw] : 0.0f;
                     const float zm = (HALO || z - k >= 0) ? cur[l - k * lw] : 0.0f;
-                    lap += a.c.w2[0][k] * ((xp + xm) - u2);
-                    lap += a.c.w2[2][k] * ((zp + zm) - u2);
+                    lap = lap_term(lap, a.c.w2[0][k], xp, xm, uc);
+                    lap = lap_term(lap, a.c.w2[2][k], zp, zm, uc);
                 }
                 float c, dmp;
                 if constexpr (kCacheCoef) {

@@ -27,20 +27,31 @@ __device__ __forceinline__ void tti_normal(const TtiArgs &a, int64_t i, float &n
     }
 }
 
+// Coupled update of p and r from A = L p - H p, B = H r (one rounding
+// pattern for every TTI kernel):
+//   p+ from (1 + 2 eps) A + sqrt(1 + 2 delta) B,  r+ from sqrt(1 + 2 delta) A + B
+__device__ __forceinline__ void tti_update(float pc, float pp, float rc, float rp, float A, float B, float m, float eps,
+                                           float delta, float dt2, float a, float &pn, float &rn) {
+#pragma clang fp contract(off)
+    const float sd = __builtin_sqrtf(__builtin_fmaf(2.0f, delta, 1.0f));
+    const float cdt = dt2 * fast_rcp(m);
+    pn = leapfrog(pc, pp, cdt * __builtin_fmaf(__builtin_fmaf(2.0f, eps, 1.0f), A, sd * B), a);
+    rn = leapfrog(rc, rp, cdt * __builtin_fmaf(sd, A, B), a);
+}
+
 // n . grad f at element i (centred first derivatives of order 2R).
 template <int NDIM, int R>
 __device__ __forceinline__ float rot_grad(const float *f, int64_t i, const Geom &g, const Coefs &c, float nx,
                                           float ny, float nz) {
+#pragma clang fp contract(off)
     float dx = 0.0f, dy = 0.0f, dz = 0.0f;
 #pragma unroll
     for (int k = 1; k <= R; ++k) {
-        dx += c.w1[0][k] * (f[i + k] - f[i - k]);
-        dz += c.w1[2][k] * (f[i + k * g.sz] - f[i - k * g.sz]);
-        if (NDIM == 3) dy += c.w1[1][k] * (f[i + k * g.sy] - f[i - k * g.sy]);
+        dx = d1_term(dx, c.w1[0][k], f[i + k], f[i - k]);
+        dz = d1_term(dz, c.w1[2][k], f[i + k * g.sz], f[i - k * g.sz]);
+        if (NDIM == 3) dy = d1_term(dy, c.w1[1][k], f[i + k * g.sy], f[i - k * g.sy]);
     }
-    float r = nx * dx + nz * dz;
-    if (NDIM == 3) r += ny * dy;
-    return r;
+    return dot3(nx, dx, ny, NDIM == 3 ? dy : 0.0f, nz, dz);
 }
 
 // TTI stage 1: gp = n . grad p, gr = n . grad r on every domain point.
@@ -65,6 +76,7 @@ __global__ void __launch_bounds__(256) tti_naive_stage1(TtiArgs a) {
 // TTI stage 2: H p = n . grad gp, H r = n . grad gr, L p, coupled update.
 template <int NDIM, int R>
 __device__ __forceinline__ void tti_stage2_point(const TtiArgs &a, int x, int y, int z) {
+#pragma clang fp contract(off)
     const int64_t i = a.g.off0 + (int64_t)z * a.g.sz + (int64_t)y * a.g.sy + x;
     float nx, ny, nz;
     tti_normal<NDIM>(a, i, nx, ny, nz);
@@ -72,20 +84,22 @@ __device__ __forceinline__ void tti_stage2_point(const TtiArgs &a, int x, int y,
     const float hr = rot_grad<NDIM, R>(a.gr, i, a.g, a.c, nx, ny, nz);
     const float pc = a.p_cur[i];
     const float lap = laplacian_at<NDIM, R>(a.p_cur, i, a.g, a.c);
-    const float A = lap - hp;
-    const float B = hr;
-    const float s = sqrtf(1.0f + 2.0f * a.delta[i]);
-    const float rm = fast_rcp(a.m[i]);
-    const float cdt = a.dt2 * rm;
     const float d = damp_at(a.eta_x, a.eta_y, a.eta_z, NDIM, x, y, z);
-    float pn = leapfrog(pc, a.p_prev[i], cdt * ((1.0f + 2.0f * a.eps[i]) * A + s * B), d);
-    float rn = leapfrog(a.r_cur[i], a.r_prev[i], cdt * (s * A + B), d);
-    if (a.src.n) {
-        pn = fused_inject(a.src, NDIM, x, y, z, rm, pn);
-        rn = fused_inject(a.src, NDIM, x, y, z, rm, rn);
+    float pn, rn;
+    tti_update(pc, a.p_prev[i], a.r_cur[i], a.r_prev[i], lap - hp, hr, a.m[i], a.eps[i], a.delta[i], a.dt2, d, pn,
+               rn);
+    const float rm = fast_rcp(a.m[i]);
+    if (a.src.n) {  // the same injected sum into p and r
+        const float inj = fused_inject(a.src, NDIM, x, y, z, rm, 0.0f);
+        pn += inj;
+        rn += inj;
     }
     a.p_next[i] = pn;
     a.r_next[i] = rn;
+    if (a.save_p) {
+        a.save_p[i] = pn;
+        a.save_r[i] = rn;
+    }
 }
 
 template <int NDIM, int R>
@@ -130,6 +144,7 @@ struct TtiS1Op {
     __device__ __forceinline__ float begin_plane(int) const { return 0.0f; }
     template <int R, class P>
     __device__ __forceinline__ void point(const P &pt, bool, float, bool live) const {
+#pragma clang fp contract(off)
         float nx, ny, nz;
         tti_normal3(pt.p(0), pt.p(1), nx, ny, nz);
 #pragma unroll
@@ -137,11 +152,11 @@ struct TtiS1Op {
             float dx = 0.0f, dy = 0.0f, dz = 0.0f;
 #pragma unroll
             for (int k = 1; k <= R; ++k) {
-                dx += c.w1[0][k] * (pt.qx(f, k) - pt.qx(f, -k));
-                dy += c.w1[1][k] * (pt.qy(f, k) - pt.qy(f, -k));
-                dz += c.w1[2][k] * (pt.qz(f, k) - pt.qz(f, -k));
+                dx = d1_term(dx, c.w1[0][k], pt.qx(f, k), pt.qx(f, -k));
+                dy = d1_term(dy, c.w1[1][k], pt.qy(f, k), pt.qy(f, -k));
+                dz = d1_term(dz, c.w1[2][k], pt.qz(f, k), pt.qz(f, -k));
             }
-            const float gv = nx * dx + ny * dy + nz * dz;
+            const float gv = dot3(nx, dx, ny, dy, nz, dz);
             if (live) pt.store(f == 0 ? gp : gr, gv);
         }
     }
@@ -158,6 +173,7 @@ struct TtiS2Op {
     float dt2;
     FusedSrc src;
     float *p_next, *r_next;
+    float *save_p, *save_r;  // optional second destination of the new levels
     __device__ __forceinline__ bool begin_tile(int x0, int tx, int y0, int ty, int z0, int z1) const {
         return src_in_tile(src, x0, tx, y0, ty, z0, z1);
     }
@@ -165,6 +181,7 @@ struct TtiS2Op {
     __device__ __forceinline__ float begin_plane(int z) const { return eta.plane(z); }
     template <int R, class P>
     __device__ __forceinline__ void point(const P &pt, bool src_here, float a, bool live) const {
+#pragma clang fp contract(off)
         float nx, ny, nz;
         tti_normal3(pt.p(6), pt.p(7), nx, ny, nz);
         float h[2];
@@ -173,35 +190,35 @@ struct TtiS2Op {
             float dx = 0.0f, dy = 0.0f, dz = 0.0f;
 #pragma unroll
             for (int k = 1; k <= R; ++k) {
-                dx += c.w1[0][k] * (pt.qx(f, k) - pt.qx(f, -k));
-                dy += c.w1[1][k] * (pt.qy(f, k) - pt.qy(f, -k));
-                dz += c.w1[2][k] * (pt.qz(f, k) - pt.qz(f, -k));
+                dx = d1_term(dx, c.w1[0][k], pt.qx(f, k), pt.qx(f, -k));
+                dy = d1_term(dy, c.w1[1][k], pt.qy(f, k), pt.qy(f, -k));
+                dz = d1_term(dz, c.w1[2][k], pt.qz(f, k), pt.qz(f, -k));
             }
-            h[f] = nx * dx + ny * dy + nz * dz;
+            h[f] = dot3(nx, dx, ny, dy, nz, dz);
         }
         const float pc = pt.qz(2, 0);
-        const float p2 = 2.0f * pc;
         float lap = 0.0f;
 #pragma unroll
         for (int k = 1; k <= R; ++k) {
-            lap += c.w2[2][k] * ((pt.qz(2, k) + pt.qz(2, -k)) - p2);
-            lap += c.w2[0][k] * ((pt.qx(2, k) + pt.qx(2, -k)) - p2);
-            lap += c.w2[1][k] * ((pt.qy(2, k) + pt.qy(2, -k)) - p2);
+            lap = lap_term(lap, c.w2[2][k], pt.qz(2, k), pt.qz(2, -k), pc);
+            lap = lap_term(lap, c.w2[0][k], pt.qx(2, k), pt.qx(2, -k), pc);
+            lap = lap_term(lap, c.w2[1][k], pt.qy(2, k), pt.qy(2, -k), pc);
         }
-        const float A = lap - h[0];
-        const float B = h[1];
-        const float sd = __builtin_sqrtf(1.0f + 2.0f * pt.p(5));
+        float pn, rn;
+        tti_update(pc, pt.p(0), pt.p(1), pt.p(2), lap - h[0], h[1], pt.p(3), pt.p(4), pt.p(5), dt2, a, pn, rn);
         const float rm = fast_rcp(pt.p(3));
-        const float cdt = dt2 * rm;
-        float pn = leapfrog(pc, pt.p(0), cdt * ((1.0f + 2.0f * pt.p(4)) * A + sd * B), a);
-        float rn = leapfrog(pt.p(1), pt.p(2), cdt * (sd * A + B), a);
         if (src_here) {
-            pn = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, pn);
-            rn = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, rn);
+            const float inj = fused_inject(src, 3, pt.x, pt.y, pt.z, rm, 0.0f);
+            pn += inj;
+            rn += inj;
         }
         if (live) {
             pt.store(p_next, pn);
             pt.store(r_next, rn);
+            if (save_p) {
+                pt.store(save_p, pn);
+                pt.store(save_r, rn);
+            }
         }
     }
 };
@@ -291,6 +308,8 @@ static void tti_stage2_parts(const TtiArgs &a, TtiS2Op &o2, StreamFields<3, 8> &
     o2.src = a.src;
     o2.p_next = a.p_next;
     o2.r_next = a.r_next;
+    o2.save_p = a.save_p;
+    o2.save_r = a.save_r;
     F2.q[0] = a.gp;
     F2.q[1] = a.gr;
     F2.q[2] = a.p_cur;

@@ -142,6 +142,29 @@ def test_tti_angles_full_turn(torch_dev, shape):
     check(prob, gf, gtr, of, otr)
 
 
+@pytest.mark.parametrize("shape,so,nt,splits", [((150, 70, 90), 8, 24, None), ((61, 53, 47), 4, 17, None),
+                                                 ((100, 90, 120), 16, 10, None), ((133, 80, 71), 8, 23, [4, 11, 12]),
+                                                 ((256, 256, 256), 8, 12, None)])
+def test_tb3d_equals_per_step(torch_dev, monkeypatch, shape, so, nt, splits):
+    """Two steps per launch (3D temporal blocking) against one launch per
+    step, bit for bit: fields and traces, odd step counts (a last per-step
+    launch) and applies split at odd points; several x/y tiles and z-chunks,
+    sources and receivers anywhere.  The oracle bar on top."""
+    prob = W.small_problem("iso", shape, so, nt=nt, seed=500 + so + nt, nsrc=2, nrec=40, nbl=6)
+    say("tb3d", shape, so, nt, splits)
+    monkeypatch.setenv("FDW_TB3D", "0")
+    f0, t0, d0 = gpu_run(prob, torch_dev, nslots=2, splits=splits)
+    monkeypatch.setenv("FDW_TB3D", "1")
+    f1, t1, d1 = gpu_run(prob, torch_dev, nslots=2, splits=splits)
+    assert "iso3d_tb2" in d1 and "iso3d_tb2" not in d0, (d0, d1)
+    np.testing.assert_array_equal(f1["u"][1], f0["u"][1])
+    np.testing.assert_array_equal(f1["u"][0], f0["u"][0])
+    np.testing.assert_array_equal(t1, t0)
+    if np.prod(shape) <= 2e6:
+        of, otr = oracle_run(prob)
+        check(prob, f1, t1, of, otr)
+
+
 @pytest.mark.parametrize("kind", ["iso", "tti"])
 def test_many_colliding_sources(torch_dev, kind):
     """More sources than the fused path holds (atomic injection), several in one cell."""

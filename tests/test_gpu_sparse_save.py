@@ -131,3 +131,55 @@ def test_subsampled_save(torch_dev, shape, nsrc, every, first, nlevels, nslots):
         assert np.linalg.norm(ref[L]) > 0 or L == 0
         assert e <= TOL, (L, e)
     assert np.all(got[nlevels] == 7.0)
+
+
+
+def oracle_tti_levels(prob):
+    """p and r at every level 0 .. nt of the oracle's run (one step per call)."""
+    g = oracle.Grid(prob.shape, prob.extent, prob.origin, so=prob.so, dt=prob.dt, nbl=prob.nbl, vmax=prob.vmax,
+                    rc=prob.rc)
+    f = prob.fields
+    z = np.zeros(prob.array_shape)
+    pp, pc, rp, rc = z.copy(), z.copy(), z.copy(), z.copy()
+    levels = [(pc.copy(), rc.copy())]
+    for t in range(prob.nt):
+        pp, pc, rp, rc, _ = oracle.tti_run(g, f["m"], f["eps"], f["delta"], f["theta"], f.get("phi"), prob.nt, pp, pc,
+                                           rp, rc, src_coords=prob.src_coords, src=prob.src, rec_coords=None,
+                                           time_m=t, time_M=t)
+        levels.append((pc.copy(), rc.copy()))
+    return levels
+
+
+@pytest.mark.parametrize("shape,nsrc,every,first,nlevels,nslots",
+                         [((41, 33, 29), 1, 4, 0, 5, 3),    # fused store in stage 2, level 0 copied
+                          ((37, 31, 26), 6, 3, 2, 5, 2),    # scatter injection: copies after the step
+                          ((71, 53), 2, 5, 1, 4, 3)])       # 2D (one thread per point)
+def test_tti_subsampled_save(torch_dev, shape, nsrc, every, first, nlevels, nslots):
+    """TTI level saving: p and r of every saved level against the oracle,
+    and nothing written past the requested levels."""
+    import torch
+
+    from paper_1807_03032_amd import fdw
+
+    prob = W.small_problem("tti", shape, 8, nt=21, seed=95 + nsrc, nsrc=nsrc, nrec=5, nbl=4)
+    say("tti save", shape, nsrc, every, first, nlevels, nslots)
+    shot = fdw.Shot(prob, torch_dev, nslots=nslots)
+    try:
+        E = shot.lay.elems_per_slot
+        buf = torch.full(((2 * nlevels + 1) * E,), 7.0, dtype=torch.float32, device=torch_dev)
+        fdw.fdw_operator_set_save(shot.op, buf.data_ptr(), nlevels, every, first)
+        shot.apply(0, prob.nt - 1)
+        torch.cuda.synchronize()
+        got = [fdw.download(buf, shot.lay, k) for k in range(2 * nlevels + 1)]
+    finally:
+        shot.close()
+    ref = oracle_tti_levels(prob)
+    saved = [L for L in range(first, prob.nt + 1, every)][:nlevels]
+    assert len(saved) == nlevels
+    for k, L in enumerate(saved):
+        for j, nm in enumerate("pr"):
+            e = rel_l2(got[2 * k + j], ref[L][j])
+            say("level", L, nm, f"{e:.2e}")
+            assert np.linalg.norm(ref[L][j]) > 0 or L == 0
+            assert e <= TOL, (L, nm, e)
+    assert np.all(got[2 * nlevels] == 7.0)
