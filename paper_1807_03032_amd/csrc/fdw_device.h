@@ -219,34 +219,74 @@ struct StreamFields {
     const float *p[NP];  // pointwise fields
 };
 
-// Raw buffer accesses for the streaming engine.  The descriptor holds a
+// Raw buffer accesses for the streaming engines.  The descriptor holds a
 // wave-uniform base (scalar registers) and a record count; the per-lane
-// offset is a 32-bit byte offset, so no per-lane 64-bit address arithmetic is
-// needed.  The hardware bounds-checks every access against the record count:
-// a load at or past it returns zero and a store there is dropped, which is how
-// the engine reads the zero Dirichlet exterior without branches or memory
-// traffic -- lanes outside the domain carry the offset kBufOut, and a plane
-// outside the domain gets a descriptor with no records.  Valid offsets stay
-// below kBufOut (a plane of the padded layout is below 2 GiB).  Descriptor
-// word 3 is the gfx9-family raw-buffer format.
+// offset is a 32-bit byte offset and the plane offset a scalar (soffset), so
+// no per-lane 64-bit address arithmetic is needed and a descriptor is built
+// once per workgroup.  The hardware bounds-checks every access against the
+// record count: a load at or past it returns zero and a store there is
+// dropped, which is how the engines read the zero Dirichlet exterior without
+// branches or memory traffic -- lanes outside the domain carry the offset
+// kBufOut, and a plane outside the domain is read with that offset on every
+// lane.  The record count is larger than any valid offset and below kBufOut,
+// so an out-of-domain offset is out of range whether or not the hardware adds
+// the scalar offset before the check.  Descriptor word 3 is the gfx9-family
+// raw-buffer format.
+//
+// Chunk-based addressing (ring engine): a workgroup walking planes [z0, z1)
+// reads planes z0 - R - PF .. z1 - 1 + R + PF at most, so its descriptors are
+// based at plane zlo = z0 - R - PF and plane z lies (z - zlo) * plane_bytes
+// further.  The launcher keeps that span, zc + 2 (R + PF) planes, below 2 GiB
+// (buffer_zchunk), which holds for fields of any size whose planes are small
+// enough (buffer_planes_fit).
 constexpr uint32_t kBufOut = 0x80000000u;
+constexpr int kRecords2 = 0x7fffffff;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc2(const float *base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, kRecords2, 0x00020000);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vb, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, soff, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vb, int soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)vb, soff, 0);
+}
+
+// Planes one chunk descriptor spans beyond the chunk itself.
+constexpr int buffer_extra_planes(int R, int PF) { return 2 * (R + PF); }
+// Can a buffer-addressed launch of this order run on these planes (a chunk
+// of one plane within the 2 GiB span)?
+inline bool buffer_planes_fit(const Geom &g, int R, int PF) {
+    return (int64_t)(1 + buffer_extra_planes(R, PF)) * g.sz * 4 < ((int64_t)1 << 31);
+}
+// z-chunk of a buffer-addressed launch: at most zc (and nz), and short enough
+// that the descriptor span stays below 2 GiB (at least 1 where the planes fit).
+inline int buffer_zchunk(int zc, const Geom &g, int R, int PF) {
+    if (zc > g.nz) zc = g.nz;
+    const int64_t fit = (((int64_t)1 << 31) - 1) / (g.sz * 4) - buffer_extra_planes(R, PF);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(zc, fit));
+}
+
+// The shifting-queue engine addresses plane by plane instead: element at byte
+// offset vb within plane zo (element offset of the plane's (0, 0),
+// wave-uniform) of a field; vb = kBufOut or valid = false (a plane outside the
+// domain) read as zero and drop stores.  BUF = true: a raw buffer descriptor
+// based at the plane (rebuilt per plane from the field pointer: with up to
+// fifteen fields, one descriptor per field and workgroup does not fit the
+// scalar registers), no branches.  BUF = false: global accesses at the
+// field's base (scalar) + a 32-bit byte offset, branching around the lanes
+// and planes outside the domain; the field must be below 4 GiB.  Each
+// operator picks the form that measures faster for it: the TTI stages, with
+// many loads per point and VALU-bound, gain from the buffer form; the
+// isotropic step, bound by HBM bandwidth, runs slightly faster with global
+// accesses.  (Global accesses name the global address space: field pointers
+// read from a record in memory, as in the multi-shot kernels, would otherwise
+// be generic and compile to flat accesses, which also count against the LDS
+// wait counter and so stall every LDS wait behind the loads in flight.)
+using gfloat = __attribute__((address_space(1))) float;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_at(const float *base, bool valid) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, valid ? (int)kBufOut : 0, 0x00020000);
 }
-// Element at byte offset vb within plane zo (element offset of the plane's
-// (0, 0), wave-uniform) of a field; vb = kBufOut or valid = false (a plane
-// outside the domain) read as zero and drop stores.  BUF = true: raw buffer
-// accesses as above, no branches.  BUF = false: global accesses at the
-// field's base (scalar) + a 32-bit byte offset, branching around the lanes
-// and planes outside the domain; the field must be below 4 GiB.  Each operator
-// picks the form that measures faster for it: the TTI stages, with many loads
-// per point and VALU-bound, gain from the buffer form; the isotropic step,
-// bound by HBM bandwidth, runs slightly faster with global accesses.
-// (Global accesses name the global address space: field pointers read from a
-// record in memory, as in the multi-shot kernels, would otherwise be generic
-// and compile to flat accesses, which also count against the LDS wait
-// counter and so stall every LDS wait behind the loads in flight.)
-using gfloat = __attribute__((address_space(1))) float;
 template <bool BUF>
 __device__ __forceinline__ float load_at(const float *f, int64_t zo, uint32_t vb, bool valid = true) {
     if constexpr (BUF)
@@ -339,6 +379,14 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
     // plane z's element (0, 0) is at pbase + z * sz; (x, y) is y * sy + x
     // elements further, or out of bounds (kBufOut) outside the domain
     const int64_t pbase = g.off0;
+    // stencil field f / pointwise field f at plane z, byte offset vb in the plane
+    // (valid = false: a plane outside the domain, read as zero)
+    auto ldq = [&](int f, int z, uint32_t vb, bool valid) -> float {
+        return load_at<BUF>(F.q[f], pbase + (int64_t)z * g.sz, vb, valid);
+    };
+    auto ldp = [&](int f, int z, uint32_t vb) -> float {
+        return load_at<BUF>(F.p[f], pbase + (int64_t)z * g.sz, vb, true);
+    };
     auto vbyte = [&](int xx, int yy) {
         return xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny ? (uint32_t)(((int64_t)yy * g.sy + xx) * 4) : kBufOut;
     };
@@ -393,23 +441,21 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
         const int nplanes = z1 - z0;
         const int zs = DIR > 0 ? z0 : z1 - 1;  // first plane walked
         auto issue = [&](PlaneLoads<NQ, NP, NY, NHY, NHX> &P, int z) {
-            const int64_t zb = pbase + (int64_t)z * g.sz;
             const int zhp = z + DIR * R;
-            const int64_t zh = pbase + (int64_t)zhp * g.sz;
             const bool hin = zhp >= 0 && zhp < g.nz;
 #pragma unroll
             for (int f = 0; f < NQ; ++f) {
 #pragma unroll
-                for (int j = 0; j < NY; ++j) P.head[f][j] = load_at<BUF>(F.q[f], zh, vcol[j], hin);
+                for (int j = 0; j < NY; ++j) P.head[f][j] = ldq(f, zhp, vcol[j], hin);
 #pragma unroll
-                for (int i = 0; i < NHY; ++i) P.hy[f][i] = load_at<BUF>(F.q[f], zb, hy_vb[i]);
+                for (int i = 0; i < NHY; ++i) P.hy[f][i] = ldq(f, z, hy_vb[i], true);
 #pragma unroll
-                for (int i = 0; i < NHX; ++i) P.hx[f][i] = load_at<BUF>(F.q[f], zb, hx_vb[i]);
+                for (int i = 0; i < NHX; ++i) P.hx[f][i] = ldq(f, z, hx_vb[i], true);
             }
 #pragma unroll
             for (int f = 0; f < NP; ++f)
 #pragma unroll
-                for (int j = 0; j < NY; ++j) P.pw[f][j] = load_at<BUF>(F.p[f], zb, vcol[j]);
+                for (int j = 0; j < NY; ++j) P.pw[f][j] = ldp(f, z, vcol[j]);
             P.pv = op.begin_plane(z);
         };
 
@@ -422,7 +468,7 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
 #pragma unroll
                 for (int k = 0; k < 2 * R; ++k) {
                     const int z = zs + DIR * (k - R);
-                    q[f][j][k] = load_at<BUF>(F.q[f], pbase + (int64_t)z * g.sz, vcol[j], z >= 0 && z < g.nz);
+                    q[f][j][k] = ldq(f, z, vcol[j], z >= 0 && z < g.nz);
                 }
         PlaneLoads<NQ, NP, NY, NHY, NHX> P[PF];
 #pragma unroll
@@ -452,24 +498,35 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
 #pragma unroll
                     for (int j = 0; j < NY; ++j) cpw[f][j] = P[s].pw[f][j];
                 if (i + PF < nplanes) issue(P[s], z + DIR * PF);
-                // plane z into LDS
+                // plane z into LDS (one branch per halo element for all fields)
 #pragma unroll
-                for (int f = 0; f < NQ; ++f) {
+                for (int f = 0; f < NQ; ++f)
 #pragma unroll
                     for (int j = 0; j < NY; ++j) lds[buf][f][R + wy * NY + j][R + lane] = q[f][j][R];
 #pragma unroll
-                    for (int h = 0; h < NHY; ++h)
-                        if (hy_act[h]) lds[buf][f][hy_lds[h]][R + lane] = chy[f][h];
+                for (int h = 0; h < NHY; ++h)
+                    if (hy_act[h])
 #pragma unroll
-                    for (int h = 0; h < NHX; ++h)
-                        if (hx_act[h]) lds[buf][f][hx_lrow[h]][hx_lcol[h]] = chx[f][h];
-                }
+                        for (int f = 0; f < NQ; ++f) lds[buf][f][hy_lds[h]][R + lane] = chy[f][h];
+#pragma unroll
+                for (int h = 0; h < NHX; ++h)
+                    if (hx_act[h])
+#pragma unroll
+                        for (int f = 0; f < NQ; ++f) lds[buf][f][hx_lrow[h]][hx_lcol[h]] = chx[f][h];
                 lds_barrier();
 #pragma unroll
                 for (int j = 0; j < NY; ++j) {
-                    StreamPoint<R, NQ, NP, NY, LH, LW, DIR, BUF> pt{q,     lds[buf], cpw,   j,
-                                                               R + wy * NY + j, R + lane, x, yb + j,
-                                                               z,     pbase + (int64_t)z * g.sz, vcol[j]};
+                    StreamPoint<R, NQ, NP, NY, LH, LW, DIR, BUF> pt{q,
+                                                                    lds[buf],
+                                                                    cpw,
+                                                                    j,
+                                                                    R + wy * NY + j,
+                                                                    R + lane,
+                                                                    x,
+                                                                    yb + j,
+                                                                    z,
+                                                                    pbase + (int64_t)z * g.sz,
+                                                                    vcol[j]};
                     // computed for every column (keeps the NY columns in one scheduling
                     // region); only stores are predicated on the column being in the domain
                     op.template point<R>(pt, tile_flag, colv[j] + plane_val, in[j]);

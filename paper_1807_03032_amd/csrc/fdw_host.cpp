@@ -537,10 +537,13 @@ static void pick_variants(fdw_op *op) {
     // FDW_KERNEL=naive forces the one-thread-per-point kernels (A/B checks).
     const char *k = std::getenv("FDW_KERNEL");
     const bool naive = k && std::strcmp(k, "naive") == 0;
-    // the streaming kernels address within a plane of the padded layout with
-    // byte offsets below 2^31 (larger offsets read as zero): planes above
-    // 2 GiB take the per-point kernels
-    const bool big_plane = op->lay.pitch_x * op->lay.pitch_y * (int64_t)sizeof(float) > ((int64_t)1 << 31);
+    // the 3D streaming kernels address a z-chunk of the padded layout with
+    // byte offsets below 2^31 from a descriptor based R + 2 planes below it:
+    // grids whose chunk of one plane, 2R + 5 planes, reaches 2 GiB take the
+    // per-point kernels (2D: fields above 2 GiB)
+    const int64_t plane_bytes = op->lay.pitch_x * op->lay.pitch_y * (int64_t)sizeof(float);
+    const bool big_plane = op->ndim == 3 ? (int64_t)(2 * op->R + 5) * plane_bytes >= ((int64_t)1 << 31)
+                                         : plane_bytes > ((int64_t)1 << 31);
     op->iso_v = naive || big_plane ? IsoVariant::Naive : IsoVariant::Stream;
     op->tti_v = naive || big_plane ? TtiVariant::Naive : TtiVariant::Stream;
     // the persistent kernel handles linear (2 x 2) sparse supports only
@@ -1340,7 +1343,7 @@ int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_b
     const char *name = iso ? (op->use_persist2d ? "iso2d_persistent (LDS-resident, one launch per apply)"
                               : op->use_tb2d    ? tbname
                               : op->use_tb3d    ? tb3d_kernel_name(op->geom, op->R)
-                                                : iso_kernel_name(op->ndim, op->iso_v, op->geom))
+                                                : iso_kernel_name(op->ndim, op->R, op->iso_v, op->geom))
                            : tti_kernel_name(op->ndim, op->tti_v, op->geom);
     snprintf(buf, (size_t)buflen, "%s so=%d R=%d ndim=%d src=%s nsrc=%d nrec=%d", name, op->d.space_order, op->R,
              op->ndim, op->src_fused ? "fused" : "kernel", op->d.src ? op->d.src->npoint : 0,

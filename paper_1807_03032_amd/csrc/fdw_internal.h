@@ -268,7 +268,7 @@ hipError_t launch_bandwidth_probe(int kind, float *dst, const float *a, const fl
                                   hipStream_t st);
 
 // Human-readable description of the launch plan of the dominant kernel.
-const char *iso_kernel_name(int ndim, IsoVariant v, const Geom &g);
+const char *iso_kernel_name(int ndim, int R, IsoVariant v, const Geom &g);
 const char *tti_kernel_name(int ndim, TtiVariant v, const Geom &g);
 
 }  // namespace fdw

@@ -93,22 +93,9 @@ static IsoShape iso_stream_shape(const Geom &g) {
 
 static IsoOp make_iso_op(const IsoArgs &a);
 
-// Fields of 4 GiB or more are beyond the global accesses' 32-bit byte
-// offsets: they take the raw buffer form (offsets within one plane).
-struct IsoOpWide : IsoOp {
-    static constexpr bool kBufferAccess = true;
-};
-// (FDW_ISO_WIDE=1 takes the wide form on any grid: checks of that path)
-static bool iso_wide_form(const Geom &g) {
-    const char *e = std::getenv("FDW_ISO_WIDE");
-    return (e && e[0] == '1') || iso_wide_fields(g);
-}
-static StreamFields<1, 2> iso_fields(const IsoArgs &a);
-
 // engine of the 3D isotropic step: the ring-buffer engine at orders up to 8
 // (FDW_ENGINE=1 forces the shifting-queue engine), the shifting-queue engine
 // above (there the ring kernel copies its operator record to scratch memory)
-// and for the wide form
 static bool iso_ring_engine(int R) {
     static const bool ring = [] {
         const char *e = std::getenv("FDW_ENGINE");
@@ -116,6 +103,19 @@ static bool iso_ring_engine(int R) {
     }();
     return ring && R <= 4;
 }
+
+// Fields of 4 GiB or more are beyond the global accesses' 32-bit byte
+// offsets: the shifting-queue engine takes its raw buffer form for them (the
+// ring engine is buffer-addressed at any size).
+struct IsoOpWide : IsoOp {
+    static constexpr bool kBufferAccess = true;
+};
+// (FDW_ISO_WIDE=1 takes the wide form on any grid: checks of that path)
+static bool iso_wide_form(const Geom &g, int R) {
+    const char *e = std::getenv("FDW_ISO_WIDE");
+    return (e && e[0] == '1') || (iso_wide_fields(g) && !iso_ring_engine(R));
+}
+static StreamFields<1, 2> iso_fields(const IsoArgs &a);
 
 template <int R, int NY, int PF, int BY>
 static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t s, const LaunchEvents &ev) {
@@ -145,7 +145,7 @@ template <int R>
 static hipError_t launch_iso3d_stream(const IsoArgs &a, hipStream_t s, const LaunchEvents &ev) {
     const IsoShape sh = iso_stream_shape(a.g);
     // FDW_ISO_WIDE=1 takes the wide form on any grid (checks of that path)
-    if (iso_wide_form(a.g))
+    if (iso_wide_form(a.g, R))
         return launch_stream3d<R, 2, 2, 4>(IsoOpWide{make_iso_op(a)}, iso_fields(a), a.g, sh.zc, s, ev.start, ev.stop,
                                            a.rec);
     if constexpr (R == 4) {
@@ -235,11 +235,11 @@ hipError_t launch_iso_multi(int ndim, int R, const Geom &g, const void *recs, in
 #undef ISO_M
 }
 
-const char *iso_kernel_name(int ndim, IsoVariant v, const Geom &g) {
+const char *iso_kernel_name(int ndim, int R, IsoVariant v, const Geom &g) {
     if (ndim == 3 && v == IsoVariant::Stream) {
         static thread_local char buf[96];
         const IsoShape sh = iso_stream_shape(g);
-        if (iso_wide_form(g))
+        if (iso_wide_form(g, R))
             std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x8 (4 waves) zchunk=%d prefetch=2 wide", sh.zc);
         else
             std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x%d (%d waves) zchunk=%d prefetch=%d", sh.by * sh.ny,

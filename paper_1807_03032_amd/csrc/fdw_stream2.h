@@ -6,9 +6,9 @@
 // operator functors), organised to issue as few instructions per point as
 // possible:
 //   * every field is read through a raw buffer descriptor built once per
-//     workgroup; a lane's 32-bit byte offset within a plane is computed once,
-//     and the plane offset is a scalar (soffset) -- per plane no address
-//     arithmetic and no descriptor rebuild.  A lane outside the domain carries
+//     workgroup, based at its chunk (see rsrc2); a lane's 32-bit byte offset
+//     within a plane is computed once, and the plane offset is a scalar
+//     (soffset) -- per plane no address arithmetic and no descriptor rebuild.  A lane outside the domain carries
 //     an offset past the descriptor's record count, so its loads read zero and
 //     its stores are dropped by the hardware bounds check, with no branch;
 //     planes outside the domain are skipped by a wave-uniform branch and read
@@ -19,8 +19,7 @@
 //     shifts between planes;
 //   * pointwise fields and the in-plane halo are prefetched PF planes ahead
 //     into rings of PF + 1 entries (the ring length is a multiple of PF + 1).
-// Fields must be below 2 GiB (32-bit offsets; larger fields take
-// stream3d_body's wide form).
+// Fields of any size whose planes fit the chunk span (buffer_planes_fit).
 #pragma once
 #include "fdw_device.h"
 
@@ -36,22 +35,6 @@ __device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int,
 template <int N, class F>
 __device__ __forceinline__ void static_for(F &&f) {
     static_for_seq(f, std::make_integer_sequence<int, N>{});
-}
-
-// Record count of every descriptor: larger than any in-field byte offset
-// (fields below 2 GiB) and below kBufOut, so an out-of-domain lane's offset
-// is out of range whether or not the hardware adds the scalar plane offset
-// before the check.
-constexpr int kRecords2 = 0x7fffffff;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc2(const float *base) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, kRecords2, 0x00020000);
-}
-__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vb, int soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, soff, 0));
-}
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vb, int soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)vb, soff, 0);
 }
 
 // Ring length: 2R + 1 + PF rounded up to a multiple of PF + 1 (pointwise
@@ -73,9 +56,9 @@ struct RingPoint {
     int slot;       // ring slot of the point's plane (compile-time after unrolling)
     int pslot;      // pointwise ring slot
     int zdir;       // +1 / -1: walking direction
-    int soff;       // byte offset of plane z from the element (0, 0, 0) (uniform)
+    int soff;       // byte offset of plane z from the chunk descriptors' base (uniform)
     uint32_t vb;    // byte offset of the column within a plane (out of range outside the domain)
-    int64_t off0;   // element offset of (0, 0, 0) in the layout
+    int64_t cbase;  // element offset of the chunk descriptors' base in the layout
     // field f at (x, y, z + k), (x + k, y, z), (x, y + k, z); k in [-R, R]
     __device__ __forceinline__ float qz(int f, int k) const {
         const int s = slot + zdir * k;
@@ -85,7 +68,7 @@ struct RingPoint {
     __device__ __forceinline__ float qy(int f, int k) const { return lds[f][ly + k][lx]; }
     __device__ __forceinline__ float p(int i) const { return pw[i][j][pslot]; }
     // stores v at the point's element of an output field in the same layout
-    __device__ __forceinline__ void store(float *f, float v) const { bstore(rsrc2(f + off0), vb, soff, v); }
+    __device__ __forceinline__ void store(float *f, float v) const { bstore(rsrc2(f + cbase), vb, soff, v); }
 };
 
 template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
@@ -116,11 +99,14 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
     auto vbyte = [&](int xx, int yy) {
         return xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny ? (uint32_t)(((int64_t)yy * g.sy + xx) * 4) : kBufOut;
     };
+    // descriptors based at plane zlo of the chunk; plane z is (z - zlo) planes further
+    const int zlo = z0 - R - PF;
+    const int64_t cbase = g.off0 + (int64_t)zlo * g.sz;
     __amdgpu_buffer_rsrc_t rq[NQ], rp[NP];
 #pragma unroll
-    for (int f = 0; f < NQ; ++f) rq[f] = rsrc2(F.q[f] + g.off0);
+    for (int f = 0; f < NQ; ++f) rq[f] = rsrc2(F.q[f] + cbase);
 #pragma unroll
-    for (int f = 0; f < NP; ++f) rp[f] = rsrc2(F.p[f] + g.off0);
+    for (int f = 0; f < NP; ++f) rp[f] = rsrc2(F.p[f] + cbase);
     const int yb = y0 + wy * NY;
     bool in[NY];
     uint32_t vcol[NY];
@@ -172,7 +158,7 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
             constexpr int S = decltype(slot_tag)::value;
             const int z = zs + DIR * j;
             if (z >= 0 && z < g.nz) {
-                const int so = z * plane_bytes;
+                const int so = (z - zlo) * plane_bytes;
 #pragma unroll
                 for (int f = 0; f < NQ; ++f)
 #pragma unroll
@@ -188,7 +174,7 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
         auto load_plane = [&](int j, auto slot_tag) __attribute__((always_inline)) {
             constexpr int P = decltype(slot_tag)::value;
             const int z = zs + DIR * j;
-            const int so = z * plane_bytes;
+            const int so = (z - zlo) * plane_bytes;
 #pragma unroll
             for (int f = 0; f < NP; ++f)
 #pragma unroll
@@ -226,16 +212,19 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
                         const int z = zs + DIR * i;
                         // plane i into LDS
 #pragma unroll
-                        for (int f = 0; f < NQ; ++f) {
+                        for (int f = 0; f < NQ; ++f)
 #pragma unroll
                             for (int c = 0; c < NY; ++c) lds[buf][f][R + wy * NY + c][R + lane] = q[f][c][cs];
 #pragma unroll
-                            for (int h = 0; h < NHY; ++h)
-                                if (hy_act[h]) lds[buf][f][hy_lds[h]][R + lane] = hy[f][h][cp];
+                        for (int h = 0; h < NHY; ++h)
+                            if (hy_act[h])
 #pragma unroll
-                            for (int h = 0; h < NHX; ++h)
-                                if (hx_act[h]) lds[buf][f][hx_lrow[h]][hx_lcol[h]] = hx[f][h][cp];
-                        }
+                                for (int f = 0; f < NQ; ++f) lds[buf][f][hy_lds[h]][R + lane] = hy[f][h][cp];
+#pragma unroll
+                        for (int h = 0; h < NHX; ++h)
+                            if (hx_act[h])
+#pragma unroll
+                                for (int f = 0; f < NQ; ++f) lds[buf][f][hx_lrow[h]][hx_lcol[h]] = hx[f][h][cp];
                         // loads of later planes: the ring head (plane i + PF + R) into the slot
                         // plane i - R - 1 left, pointwise and halo of plane i + PF
                         if (i + PF < nplanes) {
@@ -244,12 +233,12 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
                         }
                         lds_barrier();
                         const float plane_val = pv[cp];
-                        const int so = z * plane_bytes;
+                        const int so = (z - zlo) * plane_bytes;
 #pragma unroll
                         for (int c = 0; c < NY; ++c) {
                             RingPoint<R, NQ, NP, NY, LH, LW, RING, PR> pt{
                                 q, lds[buf], pw, c, R + wy * NY + c, R + lane, x, yb + c, z, cs, cp, DIR, so,
-                                vcol[c], g.off0};
+                                vcol[c], cbase};
                             op.template point<R>(pt, tile_flag, colv[c] + plane_val, true);
                         }
             });
@@ -279,6 +268,7 @@ template <int R, int NY, int PF, int BY, int NQ, int NP, class Op>
 static hipError_t launch_stream3d_ring(const Op &op, const StreamFields<NQ, NP> &F, const Geom &g, int zc,
                                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
                                        const SparseArgs *sp = nullptr) {
+    zc = buffer_zchunk(zc, g, R, PF);
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + BY * NY - 1) / (BY * NY), ntz = (g.nz + zc - 1) / zc;
     const int64_t nb = (int64_t)ntx * nty * ntz;
     SparseArgs spv{};

@@ -407,6 +407,42 @@ def test_wide_field_form(torch_dev, monkeypatch, shape, so):
     np.testing.assert_array_equal(wtr, gtr)
 
 
+def test_ring_engine_fields_above_2gib(torch_dev, monkeypatch):
+    """The ring engine's chunk-based descriptors on a field of more than 2 GiB
+    (800 x 800 x 860 at space order 8): a source and receivers in the planes
+    more than 2 GiB from the field's start, the same bits as the
+    shifting-queue engine (32-bit global offsets, valid below 4 GiB)."""
+    from paper_1807_03032_amd import fdw
+    shape, so, nt, h = (800, 800, 860), 8, 8, 10.0
+    ext = tuple(h * (k - 1) for k in shape)
+    m = np.full(tuple(reversed(shape)), 1.0 / 1500.0 ** 2, dtype=np.float32)  # numpy order (z, y, x)
+    m[430:] = 1.0 / 2500.0 ** 2
+    dt = W.cfl_dt(h, 2500.0, 3)
+    src_c = np.array([[4003.0, 3991.0, 8455.0]])
+    rec_c = np.array([[3950.0 + 20.0 * k, 4010.0, 8420.0 + 7.0 * k] for k in range(8)])
+    src = np.asarray(W.ricker(60.0, 0.0, dt, nt), dtype=np.float32).reshape(nt, 1)
+    prob = W.Problem("ring_2gib", "iso", shape, ext, (0.0,) * 3, so, 4, nt, dt, 2500.0, 0.0, {"m": m}, src_c, src,
+                     rec_c)
+    say("ring engine above 2 GiB", shape, so)
+    runs = []
+    for eng in ("0", "1"):
+        monkeypatch.setenv("FDW_ENGINE", eng)
+        shot = fdw.Shot(prob, torch_dev, nslots=2)
+        try:
+            if eng == "0":
+                assert shot.lay.elems_per_slot * 4 > 2 ** 31, shot.lay.elems_per_slot
+            shot.apply(0, nt - 1)
+            f = shot.fields(nt - 1)["u"]
+            runs.append((f[0][780:], f[1][780:], shot.traces()))
+        finally:
+            shot.close()
+    (p0, c0, t0), (p1, c1, t1) = runs
+    assert np.abs(c0).max() > 0 and np.abs(t0).max() > 0
+    np.testing.assert_array_equal(c0, c1)
+    np.testing.assert_array_equal(p0, p1)
+    np.testing.assert_array_equal(t0, t1)
+
+
 @pytest.mark.parametrize("kind,shape,so", [("iso", (37, 29, 23), 8), ("tti", (33, 27, 21), 12), ("iso", (67, 45), 4),
                                            ("tti", (48, 39), 8), ("iso", (70, 41, 9), 16)])
 def test_parameter_halos_are_not_read(torch_dev, kind, shape, so):
@@ -478,11 +514,12 @@ def test_tti_parameters_read_at_each_apply(torch_dev):
         np.testing.assert_array_equal(tr, rtr)
 
 
-def wide_problems():
+def wide_problems(so=8, nt=10):
     """(101^3 run, 1056 x 1040 x 1040 run) around the same source on a node:
-    constant model, no damping layer, so = 8, 10 steps, receivers within 40
-    points of the source."""
-    h, so, nt, v = 10.0, 8, 10, 2000.0
+    constant model, no damping layer, so = 8 and 10 steps (or as given, with
+    nt * so / 2 below 50 points), receivers within 40 points of the source."""
+    h, v = 10.0, 2000.0
+    assert nt * so // 2 < 50
     dt = W.cfl_dt(h, v, 3)
     src = W.f32(W.ricker(15.0, 1.0 / 15.0, dt, nt)).reshape(nt, 1)
     offs = np.array([[0.0, 0.0, 0.0], [103.7, 51.2, -77.5], [-250.0, 120.0, 30.3], [12.5, -310.0, 205.0]])
@@ -496,17 +533,19 @@ def wide_problems():
     return problem((101, 101, 101), (50, 50, 50)), problem((1056, 1040, 1040), (528, 520, 520))
 
 
-def test_wide_fields_at_real_size(torch_dev):
-    """A grid whose padded fields pass 4 GiB (1056 x 1040 x 1040, so = 8:
-    4.9 GB per field) takes the raw-buffer form of the isotropic step.  With a
-    constant model, a source on a node in the middle and no damping layer, 10
-    steps reach 40 points from the source, so the block around it must equal,
-    bit for bit, the same block of a 101^3 run around the same source (whose
-    boundary lies beyond the reach), and match the oracle's 101^3 run."""
+@pytest.mark.parametrize("so,nt", [(8, 10), (16, 6)])
+def test_wide_fields_at_real_size(torch_dev, so, nt):
+    """A grid whose padded fields pass 4 GiB (1056 x 1040 x 1040: 4.9 GB per
+    field): at so = 8 the ring engine (chunk-based buffer descriptors), at
+    so = 16 the raw-buffer form of the shifting-queue engine.  With a constant
+    model, a source on a node in the middle and no damping layer, nt steps
+    reach nt * so / 2 < 50 points from the source, so the block around it must
+    equal, bit for bit, the same block of a 101^3 run around the same source
+    (whose boundary lies beyond the reach), and match the oracle's 101^3 run."""
     import torch
 
     from paper_1807_03032_amd import fdw
-    small, big = wide_problems()
+    small, big = wide_problems(so, nt)
     so, nt = big.so, big.nt
     g = fdw.fdw_grid_create(big.shape, big.extent)
     lay = fdw.fdw_field_layout(g, so)
@@ -517,7 +556,8 @@ def test_wide_fields_at_real_size(torch_dev):
     assert "wide" not in sdesc
     shot = fdw.Shot(big, torch_dev, nslots=2)
     try:
-        assert "wide" in fdw.fdw_operator_describe(shot.op)[0]
+        desc = fdw.fdw_operator_describe(shot.op)[0]
+        assert ("wide" in desc) == (so > 8), desc
         shot.apply(0, nt - 1)
         torch.cuda.synchronize(torch_dev)
         blocks = []
