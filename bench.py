@@ -378,7 +378,7 @@ def cpu_baseline(prob, nsteps):
 # ---------------------------------------------------------------------------
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {
-    "iso": ["fdw_device.h", "fdw_iso.hip", "fdw_internal.h"],
+    "iso": ["fdw_device.h", "fdw_stream2.h", "fdw_iso_op.h", "fdw_iso.hip", "fdw_internal.h"],
     "tti": ["fdw_device.h", "fdw_tti.hip", "fdw_internal.h"],
 }
 CALIB_BYTES = 256 * 1024 * 1024
@@ -440,6 +440,20 @@ def summarize_traffic(fetch_csv, write_csv):
             e[f"{counter}_bytes"] = statistics.median(vals) * 1024.0 * factors[counter]
             e["dispatches"] = len(vals)
     return out
+
+
+def iso_kernel_match(desc):
+    """Kernel-name fragments of the isotropic operator described by desc: the
+    streaming kernel's template arguments <R, NY, PF, NQ, NP, BY> follow from
+    its tile, wavefront count and prefetch distance (one-thread-per-point
+    kernels otherwise)."""
+    import re
+
+    m = re.search(r"tile=64x(\d+) \((\d+) waves\).*prefetch=(\d+).* R=(\d+)", desc)
+    if not m:
+        return ["iso_naive"]
+    ty, by, pf, r = (int(v) for v in m.groups())
+    return [f"<{r}, {ty // by}, {pf}, 1, 2, {by}, fdw::IsoOp>"]
 
 
 def load_traffic(kind, desc):
@@ -566,7 +580,7 @@ def main():
                    "wavefield_storage": "in-place leapfrog, 2 slots" if args.nslots == 2 else "modulo-3 buffer"},
         "roofline": roofline(prob, kms, launches, alg_bytes, load_traffic("iso", desc), att_gbs),
     }
-    ops_seen = [{"desc": desc, "source_hash": source_hash("iso"), "kernel_match": ["IsoOp", "iso_naive"]}]
+    ops_seen = [{"desc": desc, "source_hash": source_hash("iso"), "kernel_match": iso_kernel_match(desc)}]
     par = parity_vs_stored("3d_iso_256", prob, steps, tr, f)
     if par is not None:
         line["parity_rel_l2_sampled"] = par
@@ -583,7 +597,7 @@ def main():
                           "kernel": d5, "steps": steps, "value": round(p5.npoints * steps / w5 / 1e9, 3),
                           "unit": "GPts/s", "ms_per_step": round(w5 * 1e3 / steps, 5),
                           "roofline": roofline(p5, k5, l5, b5, load_traffic("iso", d5), att_gbs)}
-        ops_seen.append({"desc": d5, "source_hash": source_hash("iso"), "kernel_match": ["IsoOp", "iso_naive"]})
+        ops_seen.append({"desc": d5, "source_hash": source_hash("iso"), "kernel_match": iso_kernel_match(d5)})
         del p5
     if not args.no_tti:
         tsteps = args.tti_steps or steps
