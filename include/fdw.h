@@ -241,6 +241,40 @@ int fdw_operator_apply_noalloc(fdw_op *op, int time_m, int time_M, void *stream)
  * Errors: FDW_ERR_ARG (every < 1, nlevels < 0). */
 int fdw_operator_set_save(fdw_op *op, float *buf, int64_t nlevels, int every, int first_level);
 
+/* Imaging factors of forward steps (the time derivatives the gradient with
+ * respect to m needs, Section 3.2's adjoint pairing of injection and
+ * interpolation): while set, every step t of an apply with
+ * first_step <= t < first_step + nsteps also stores
+ *   S(t) = (u(t+1) - 2 u(t) + u(t-1)) + a (u(t+1) - u(t-1)),  a = eta dt / 2,
+ * (the imaging bracket times dt^2, from the final level t + 1, sources
+ * included) at buf + (t - first_step) * elems_per_slot, same layout, halos
+ * untouched; buf holds nsteps slots.  The 3D streaming kernels store it
+ * themselves when the sources are fused (4 bytes per point and step more
+ * traffic); otherwise a standalone kernel follows the step.  buf = NULL
+ * disables it.  Isotropic forward operators whose wavefield has three time
+ * slots (u(t-1) must survive the step).
+ * Errors: FDW_ERR_ARG (kind or mode, fewer than three slots, nsteps < 1,
+ * first_step < 0). */
+int fdw_operator_set_imaging_save(fdw_op *op, float *buf, int64_t nsteps, int first_step);
+
+/* Adjoint steps time_m .. time_M of the isotropic adjoint operator `adj`
+ * (reversed time: adjoint step tau is forward step nt - 1 - tau) with the
+ * zero-lag imaging condition accumulated on `stream`:
+ *   grad -= nu(tau + 1) S(nt - 1 - tau) / dt^2
+ * for every step of the range, nu(tau + 1) being the level the step computes
+ * (its injected residuals included) and S the imaging factors stored by
+ * fdw_operator_set_imaging_save (factor of forward step t at
+ * imaging + (t - first_step) * elems_per_slot).  The 3D streaming kernels fold
+ * the imaging of a level into the next step's launch (it reads that level
+ * anyway), the last level of the range getting a launch of its own; other
+ * schedules launch it after every step.  Calls over consecutive ranges
+ * accumulate the same sums in the same order as one call over their union.
+ * grad: one slot in the operator's layout.
+ * Errors: FDW_ERR_ARG (kind or mode, steps outside 0 .. nt - 1, forward steps
+ * of the range not all among the nsteps factors), FDW_ERR_DEVICE. */
+int fdw_gradient_apply(fdw_op *adj, int time_m, int time_M, int nt, const float *imaging, int first_step,
+                       int64_t nsteps, float *grad, void *stream);
+
 /* Adjoint-state gradient with respect to m (zero-lag imaging condition of the
  * isotropic operator of `op`): for one step t,
  *   grad += -nu [(u(t+1) - 2 u(t) + u(t-1)) / dt^2 + eta (u(t+1) - u(t-1)) / (2 dt)]

@@ -69,6 +69,22 @@ __device__ __forceinline__ float dot3(float nx, float dx, float ny, float dy, fl
     return __builtin_fmaf(nz, dz, __builtin_fmaf(ny, dy, nx * dx));
 }
 
+// Zero-lag imaging condition of the gradient with respect to m (the adjoint
+// state nu times the time derivatives of the forward field, Section 3.2's
+// injection being the adjoint of interpolation):
+//   dJ/dm -= nu(t+1) [(u+ - 2u + u-)/dt^2 + eta (u+ - u-)/(2 dt)].
+// imaging_factor is the bracket times dt^2, (u+ - 2u + u-) + a (u+ - u-)
+// with a = eta dt / 2, from levels t + 1, t, t - 1 of one point;
+// image_update accumulates one term, g - (nu S) / dt^2.
+__device__ __forceinline__ float imaging_factor(float un, float uc, float up, float a) {
+#pragma clang fp contract(off)
+    return ((un - uc) - (uc - up)) + a * (un - up);
+}
+__device__ __forceinline__ float image_update(float g, float nu, float s, float inv_dt2) {
+#pragma clang fp contract(off)
+    return g - (nu * s) * inv_dt2;
+}
+
 // Laplacian at element i as sum over axes and k of w_k ((u(+k) + u(-k)) - 2u).
 // Summing differences instead of a separate centre weight keeps L exactly
 // zero on constants after the weights are rounded to float.

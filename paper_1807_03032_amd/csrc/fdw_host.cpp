@@ -125,6 +125,10 @@ struct fdw_op {
     float *save_buf = nullptr;
     int64_t save_nlevels = 0;
     int save_every = 1, save_first = 0;
+    // imaging factors of forward steps first .. first + n - 1 (isotropic forward)
+    float *isave_buf = nullptr;
+    int64_t isave_n = 0;
+    int isave_first = 0;
     // host copies of the fused-source description
     FusedSrc fsrc_template;
     bool src_fused = false;
@@ -981,9 +985,18 @@ static int timing_close(fdw_op *op, hipStream_t s) {
     return FDW_OK;
 }
 
+// Imaging condition along an adjoint apply: the factor of forward step t at
+// s + (t - first) E, paired with adjoint level T - t, accumulated into grad.
+struct ImageRun {
+    const float *s;
+    int first, T;
+    float *grad;
+};
+
 // The apply loop.  stage: the TTI gradient buffers (gp | gr, elems_per_slot
 // each); timed: the operator's kernel timing (which creates events) applies.
-static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *stage, bool timed) {
+static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *stage, bool timed,
+                      const ImageRun *img = nullptr) {
     if (!op) return fail(FDW_ERR_ARG, "operator_apply: NULL op");
     const fdw_op_desc &d = op->d;
     hipStream_t s = (hipStream_t)stream;
@@ -1012,7 +1025,8 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
     SparseArgs itp = sparse_template(op, d.rec, true);
 
     // small 2D isotropic grids: the whole range in one persistent launch
-    if (d.kind == FDW_ISO && op->ndim == 2 && op->use_persist2d && !op->save_buf && time_M >= time_m) {
+    if (d.kind == FDW_ISO && op->ndim == 2 && op->use_persist2d && !op->save_buf && !op->isave_buf &&
+        time_M >= time_m) {
         Persist2DArgs pa;
         persist2d_args(op, time_m, time_M, pa);
         LaunchEvents ev;
@@ -1026,7 +1040,7 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
     // levels from one pair of buffers and writing its two output levels to the
     // other; the pass count fixes which pair the first pass reads so that the
     // last pass writes the TimeFunction's slots (level k in slot k mod 2)
-    if (op->use_tb2d && !op->save_buf && time_M >= time_m) {
+    if (op->use_tb2d && !op->save_buf && !op->isave_buf && time_M >= time_m) {
         const TB2DShape sh = tb2d_shape(op->R);
         const int N = time_M - time_m + 1, P = (N + sh.k - 1) / sh.k;
         float *tfb = d.u->d, *scb = op->d_tb;
@@ -1076,7 +1090,7 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
     // the TimeFunction's slots; receivers of a pass are sampled inside the
     // next pass, those of the last pass by their own launches; an odd last
     // step runs the per-step kernel below
-    if (op->use_tb3d && !op->save_buf && time_M - time_m + 1 >= 2) {
+    if (op->use_tb3d && !op->save_buf && !op->isave_buf && time_M - time_m + 1 >= 2) {
         const int P = (time_M - time_m + 1) / 2;
         float *A = d.u->d, *B = op->d_tb;
         if (P % 2 == 1) {
@@ -1138,6 +1152,22 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
     // saved level k occupies `fields` slots of the buffer (isotropic: u;
     // TTI: p then r)
     const int fields = d.kind == FDW_TTI ? 2 : 1;
+    // the 3D streaming kernels store a step's imaging factor, and image the
+    // centre level of an adjoint step, themselves (the factor needs the final
+    // new level: fused sources only); elsewhere standalone kernels follow the
+    // step
+    const bool stream3d = op->ndim == 3 && d.kind == FDW_ISO && op->iso_v == IsoVariant::Stream;
+    const bool fuse_isave = stream3d && (op->src_fused || nsrc == 0);
+    const float inv_dt2 = (float)(1.0 / (d.dt * d.dt));
+    auto image_args = [&]() {
+        ImageArgs ia{};
+        ia.g = op->geom;
+        ia.eta_x = op->d_eta;
+        ia.eta_y = op->d_eta + op->geom.nx;
+        ia.eta_z = eta_z;
+        ia.inv_dt2 = inv_dt2;
+        return ia;
+    };
     // the initial level 0 is no step's output: an apply from time 0 stores it
     if (op->save_buf && time_m == 0 && time_M >= time_m && op->save_first <= 0 && op->save_first % op->save_every == 0 &&
         -op->save_first / op->save_every < op->save_nlevels) {
@@ -1159,7 +1189,11 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
         if (int st = (timed ? timing_next(op, ev) : FDW_OK)) return st;
         hipError_t e;
         float *next_field;
+        const float *cur_field = nullptr, *prev_field = nullptr;
         float *save_dst = nullptr;
+        float *isave_dst = nullptr;
+        if (op->isave_buf && t >= op->isave_first && t - op->isave_first < op->isave_n)
+            isave_dst = op->isave_buf + (int64_t)(t - op->isave_first) * E;
         {
             const int L = t + 1;
             if (op->save_buf && L >= op->save_first && (L - op->save_first) % op->save_every == 0 &&
@@ -1177,8 +1211,16 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
                 a.rec = &prev_itp;
             }
             if (save_dst && (op->src_fused || nsrc == 0)) a.save = save_dst;
+            if (isave_dst && fuse_isave) a.isave = isave_dst;
+            if (img && stream3d && t > time_m) {  // centre level t pairs with forward step T - t
+                a.img_s = img->s + (int64_t)(img->T - t - img->first) * E;
+                a.grad = img->grad;
+                a.inv_dt2 = inv_dt2;
+            }
             e = launch_iso(op->ndim, op->R, op->iso_v, a, s, ev);
             next_field = a.u_next;
+            cur_field = a.u_cur;
+            prev_field = a.u_prev;
         } else {
             TtiArgs a;
             tti_step_args(op, t, a, stage);
@@ -1211,6 +1253,25 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
             if (e == hipSuccess && d.kind == FDW_TTI)
                 e = hipMemcpyAsync(save_dst + E, d.r->d + sn * E, sizeof(float) * (size_t)E, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return fail_hip(e, "operator_apply: save copy");
+        }
+        if (isave_dst && !fuse_isave) {
+            ImageArgs ia = image_args();
+            ia.u_next = next_field;
+            ia.u_cur = cur_field;
+            ia.u_prev = prev_field;
+            ia.s_out = isave_dst;
+            if ((e = launch_imaging_factor(op->ndim, ia, s)) != hipSuccess)
+                return fail_hip(e, "operator_apply: imaging factor launch");
+        }
+        // imaging of the new level: here for the steps that do not fuse it,
+        // after the last step for those that do
+        if (img && (!stream3d || t == time_M)) {
+            ImageArgs ia = image_args();
+            ia.nu = next_field;
+            ia.s_in = img->s + (int64_t)(img->T - 1 - t - img->first) * E;
+            ia.grad = img->grad;
+            if ((e = launch_image_update(op->ndim, ia, s)) != hipSuccess)
+                return fail_hip(e, "gradient_apply: imaging launch");
         }
         if (nrec > 0 && (!fuse_interp || t == time_M)) {
             itp.field = next_field;
@@ -1255,6 +1316,47 @@ int fdw_operator_set_save(fdw_op *op, float *buf, int64_t nlevels, int every, in
     op->save_every = buf ? every : 1;
     op->save_first = buf ? first_level : 0;
     return FDW_OK;
+}
+
+int fdw_operator_set_imaging_save(fdw_op *op, float *buf, int64_t nsteps, int first_step) {
+    FDW_GUARD_BEGIN
+    if (!op) return fail(FDW_ERR_ARG, "set_imaging_save: NULL op");
+    if (!buf) {
+        op->isave_buf = nullptr;
+        op->isave_n = 0;
+        op->isave_first = 0;
+        return FDW_OK;
+    }
+    if (op->d.kind != FDW_ISO || op->d.mode != FDW_FORWARD)
+        return fail(FDW_ERR_ARG, "set_imaging_save: isotropic forward operators only");
+    if (op->d.u->nslots < 3)
+        return fail(FDW_ERR_ARG, "set_imaging_save: the wavefield needs three time slots (has %d)", op->d.u->nslots);
+    if (nsteps < 1 || first_step < 0)
+        return fail(FDW_ERR_ARG, "set_imaging_save: nsteps must be >= 1 and first_step >= 0");
+    op->isave_buf = buf;
+    op->isave_n = nsteps;
+    op->isave_first = first_step;
+    return FDW_OK;
+    FDW_GUARD_END
+}
+
+int fdw_gradient_apply(fdw_op *adj, int time_m, int time_M, int nt, const float *imaging, int first_step,
+                       int64_t nsteps, float *grad, void *stream) {
+    FDW_GUARD_BEGIN
+    if (!adj || !imaging || !grad) return fail(FDW_ERR_ARG, "gradient_apply: NULL argument");
+    if (adj->d.kind != FDW_ISO || adj->d.mode != FDW_ADJOINT)
+        return fail(FDW_ERR_ARG, "gradient_apply: isotropic adjoint operators only");
+    if (time_m < 0 || time_M >= nt || nt < 1)
+        return fail(FDW_ERR_ARG, "gradient_apply: steps %d .. %d outside 0 .. nt - 1 = %d", time_m, time_M, nt - 1);
+    if (time_M < time_m) return FDW_OK;
+    // adjoint step tau pairs its new level with forward step nt - 1 - tau
+    if (nt - 1 - time_M < first_step || nt - 1 - time_m >= first_step + nsteps)
+        return fail(FDW_ERR_ARG,
+                    "gradient_apply: forward steps %d .. %d not all among the %lld imaging factors from step %d",
+                    nt - 1 - time_M, nt - 1 - time_m, (long long)nsteps, first_step);
+    const ImageRun run{imaging, first_step, nt, grad};
+    return apply_impl(adj, time_m, time_M, stream, adj->d_stage, true, &run);
+    FDW_GUARD_END
 }
 
 int fdw_gradient_accumulate(fdw_op *op, const float *nu, const float *u_next, const float *u_cur,

@@ -56,6 +56,12 @@ struct IsoArgs {
     FusedSrc src;
     int adjoint;   // 1: injected terms are divided by the damping factor (1 + a)
     float *save;   // optional: the new level is also stored here (same layout)
+    float *isave;  // optional: the step's imaging factor is stored here (3D streaming kernels)
+    // optional (3D streaming kernels): imaging condition of the centre level,
+    // grad -= u_cur img_s / dt^2
+    const float *img_s;
+    float *grad;
+    float inv_dt2;
     const struct SparseArgs *rec;  // optional: receiver sampling of the previous step
 };
 
@@ -248,6 +254,20 @@ struct GradArgs {
     float inv_dt2;                       // 1 / dt^2
 };
 hipError_t launch_gradient(int ndim, const GradArgs &a, hipStream_t s);
+// Standalone imaging kernels (where the step kernels do not fuse them):
+// S = imaging_factor(u_next, u_cur, u_prev, a) into grad's place (ImageArgs
+// .s_out), and grad -= nu S / dt^2.
+struct ImageArgs {
+    Geom g;
+    const float *u_next, *u_cur, *u_prev;  // factor: levels t + 1, t, t - 1
+    float *s_out;
+    const float *nu, *s_in;                // update: adjoint level and factor
+    float *grad;
+    const float *eta_x, *eta_y, *eta_z;
+    float inv_dt2;
+};
+hipError_t launch_imaging_factor(int ndim, const ImageArgs &a, hipStream_t s);
+hipError_t launch_image_update(int ndim, const ImageArgs &a, hipStream_t s);
 hipError_t launch_zero_halo(int ndim, const Geom &g, int R, int64_t pitch_x, int64_t pitch_y,
                             int64_t planes, float *base, hipStream_t s);
 

@@ -139,11 +139,55 @@ static hipError_t launch_iso3d_stream_ny(const IsoArgs &a, const IsoShape &sh, h
     return launch_iso3d_stream_by<R, NY, 1>(a, sh, s, ev);
 }
 
+// Adjoint step fused with the imaging condition of its centre level (IsoImgOp:
+// pointwise u(t-1), m, imaging factor, gradient), in one tile shape per order:
+// 64 x 8, four wavefronts; loads one plane ahead in the ring engine (two
+// would exceed its 128 registers at order 8), two in the shifting-queue one.
+struct IsoImgOpWide : IsoImgOp {
+    static constexpr bool kBufferAccess = true;
+};
+// Its z-chunk: the longest of 64, 32, 16 ... planes whose 64 x 8 tile chunks
+// still fill nine tenths of the chip's 1024 four-wavefront workgroup slots
+// (it moves 28 bytes per point, 4 of them re-read at chunk ends: 320^3 with
+// 64-plane chunks, 1000 workgroups, 0.32 s per 1500-step gradient against
+// 0.35 s with the forward step's 32).
+static int image_zchunk(const Geom &g) {
+    const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
+    int zc = 64;
+    while (zc > 4 && cols * ((g.nz + zc - 1) / zc) < 920) zc /= 2;
+    return std::min(zc, g.nz);
+}
+
+template <int R>
+static hipError_t launch_iso3d_image(const IsoArgs &a, int zc, hipStream_t s, const LaunchEvents &ev) {
+    IsoImgOp op;
+    static_cast<IsoOp &>(op) = make_iso_op(a);
+    op.grad = a.grad;
+    op.inv_dt2 = a.inv_dt2;
+    StreamFields<1, 4> F;
+    F.q[0] = a.u_cur;
+    F.p[0] = a.u_prev;
+    F.p[1] = a.m;
+    F.p[2] = a.img_s;
+    F.p[3] = a.grad;
+    if constexpr (R <= 4) {
+        if (iso_ring_engine(R))
+            return launch_stream3d_ring<R, 2, 1, 4>(op, F, a.g, zc, s, ev.start, ev.stop, a.rec);
+    }
+    if (iso_wide_form(a.g, R)) {
+        IsoImgOpWide w;
+        static_cast<IsoImgOp &>(w) = op;
+        return launch_stream3d<R, 2, 2, 4>(w, F, a.g, zc, s, ev.start, ev.stop, a.rec);
+    }
+    return launch_stream3d<R, 2, 2, 4>(op, F, a.g, zc, s, ev.start, ev.stop, a.rec);
+}
+
 // Tuning variants are instantiated for R = 4 (space order 8) only; other
 // orders use the default shape.
 template <int R>
 static hipError_t launch_iso3d_stream(const IsoArgs &a, hipStream_t s, const LaunchEvents &ev) {
     const IsoShape sh = iso_stream_shape(a.g);
+    if (a.img_s) return launch_iso3d_image<R>(a, image_zchunk(a.g), s, ev);
     // FDW_ISO_WIDE=1 takes the wide form on any grid (checks of that path)
     if (iso_wide_form(a.g, R))
         return launch_stream3d<R, 2, 2, 4>(IsoOpWide{make_iso_op(a)}, iso_fields(a), a.g, sh.zc, s, ev.start, ev.stop,
@@ -180,6 +224,7 @@ static IsoOp make_iso_op(const IsoArgs &a) {
     op.src = a.src;
     op.u_next = a.u_next;
     op.save = a.save;
+    op.isave = a.isave;
     op.adjoint = a.adjoint;
     return op;
 }

@@ -41,6 +41,7 @@ struct IsoOp {
     FusedSrc src;
     float *u_next;
     float *save;   // optional second destination of the new level
+    float *isave;  // optional: the step's imaging factor (from u(t+1), u(t), u(t-1), a)
     int adjoint;   // injected terms divided by (1 + a)
     // does a fused source touch this tile and chunk?
     __device__ __forceinline__ bool begin_tile(int x0, int tx, int y0, int ty, int z0, int z1) const {
@@ -55,6 +56,26 @@ struct IsoOp {
         if (live) {
             pt.store(u_next, v);
             if (save) pt.store(save, v);
+            if (isave) pt.store(isave, imaging_factor(v, pt.qz(0, 0), pt.p(0), a));
+        }
+    }
+};
+
+// ---- adjoint step with the imaging condition of the previous step ----------
+// Pointwise fields u(t-1), m as above, then the imaging factor S of the
+// forward step paired with the centre level and the gradient: the centre
+// level nu (final: the previous launch's injections included) images
+// grad -= nu S / dt^2 at each point, beside the step itself.
+struct IsoImgOp : IsoOp {
+    float *grad;
+    float inv_dt2;
+    template <int R, class P>
+    __device__ __forceinline__ void point(const P &pt, bool src_here, float a, bool live) const {
+        const float v = iso_point_value<R>(pt, c, dt2, &src, src.q, src_here, a, adjoint);
+        if (live) {
+            pt.store(u_next, v);
+            if (save) pt.store(save, v);
+            pt.store(grad, image_update(pt.p(3), pt.qz(0, 0), pt.p(2), inv_dt2));
         }
     }
 };

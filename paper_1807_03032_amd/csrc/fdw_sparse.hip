@@ -64,6 +64,31 @@ __global__ void __launch_bounds__(256) gradient_kernel(GradArgs a) {
     a.grad[i] -= a.nu[i] * s * a.inv_dt2;
 }
 
+// Standalone imaging kernels, one thread per domain point, for the steps whose
+// kernels do not fuse the imaging condition (2D grids, one-thread-per-point
+// schedules, injections by the scatter kernel): the factor of a forward step
+// from its three levels, and the update of the gradient from an adjoint level.
+template <int NDIM>
+__global__ void __launch_bounds__(256) imaging_factor_kernel(ImageArgs a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
+    const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+    const int64_t i = a.g.off0 + (int64_t)z * a.g.sz + (int64_t)y * a.g.sy + x;
+    const float damp = damp_at(a.eta_x, a.eta_y, a.eta_z, NDIM, x, y, z);
+    a.s_out[i] = imaging_factor(a.u_next[i], a.u_cur[i], a.u_prev[i], damp);
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(256) image_update_kernel(ImageArgs a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = NDIM == 3 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : 0;
+    const int z = NDIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (x >= a.g.nx || y >= a.g.ny || z >= a.g.nz) return;
+    const int64_t i = a.g.off0 + (int64_t)z * a.g.sz + (int64_t)y * a.g.sy + x;
+    a.grad[i] = image_update(a.grad[i], a.nu[i], a.s_in[i], a.inv_dt2);
+}
+
 // Writes zero to every element of one slot outside the domain.
 __global__ void __launch_bounds__(256) zero_halo_kernel(int ndim, Geom g, int R, int64_t pitch_x,
                                                         int64_t pitch_y, int64_t planes, float *base) {
@@ -133,6 +158,32 @@ hipError_t launch_gradient(int ndim, const GradArgs &a, hipStream_t s) {
         dim3 grd((a.g.nx + 63) / 64, (a.g.nz + 3) / 4, 1);
         hipLaunchKernelGGL(gradient_kernel<2>, grd, blk, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+// one thread per domain point: 64 x 4 threads per workgroup
+static void point_grid(int ndim, const Geom &g, dim3 &grd, dim3 &blk) {
+    blk = dim3(64, 4, 1);
+    grd = ndim == 3 ? dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz) : dim3((g.nx + 63) / 64, (g.nz + 3) / 4, 1);
+}
+
+hipError_t launch_imaging_factor(int ndim, const ImageArgs &a, hipStream_t s) {
+    dim3 grd, blk;
+    point_grid(ndim, a.g, grd, blk);
+    if (ndim == 3)
+        hipLaunchKernelGGL(imaging_factor_kernel<3>, grd, blk, 0, s, a);
+    else
+        hipLaunchKernelGGL(imaging_factor_kernel<2>, grd, blk, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_image_update(int ndim, const ImageArgs &a, hipStream_t s) {
+    dim3 grd, blk;
+    point_grid(ndim, a.g, grd, blk);
+    if (ndim == 3)
+        hipLaunchKernelGGL(image_update_kernel<3>, grd, blk, 0, s, a);
+    else
+        hipLaunchKernelGGL(image_update_kernel<2>, grd, blk, 0, s, a);
     return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ EXPORTS = (
     "fdw_sparse_bind_precomputed", "fdw_batch_create", "fdw_batch_apply", "fdw_batch_stats", "fdw_batch_destroy",
     "fdw_server_create", "fdw_server_footprint", "fdw_server_submit", "fdw_server_progress", "fdw_server_info",
     "fdw_server_fetch", "fdw_server_release", "fdw_server_stats", "fdw_server_destroy", "fdw_bandwidth_probe",
-    "fdw_operator_apply_noalloc",
+    "fdw_operator_apply_noalloc", "fdw_operator_set_imaging_save", "fdw_gradient_apply",
 )
 FDW_SHOT_QUEUED, FDW_SHOT_RUNNING, FDW_SHOT_DONE, FDW_SHOT_FAILED = 0, 1, 2, 3
 
@@ -130,6 +130,8 @@ def load(path: str = LIB_PATH):
         "fdw_stable_dt": (dbl, [i32, i32, i32, dbl, dbl, dbl]),
         "fdw_operator_set_save": (i32, [vp, vp, i64, i32, i32]),
         "fdw_gradient_accumulate": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+        "fdw_operator_set_imaging_save": (i32, [vp, vp, i64, i32]),
+        "fdw_gradient_apply": (i32, [vp, i32, i32, i32, vp, i32, i64, vp, vp]),
         "fdw_batch_create": (i32, [pvp]),
         "fdw_batch_apply": (i32, [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]),
         "fdw_batch_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
@@ -279,6 +281,15 @@ def fdw_operator_set_save(op, buf: Optional[int], nlevels: int = 0, every: int =
 def fdw_gradient_accumulate(op, nu: int, u_next: int, u_cur: int, u_prev: int, grad: int,
                             stream: Optional[int] = None):
     _chk(load().fdw_gradient_accumulate(op, nu, u_next, u_cur, u_prev, grad, stream))
+
+
+def fdw_operator_set_imaging_save(op, buf: Optional[int], nsteps: int = 0, first_step: int = 0):
+    _chk(load().fdw_operator_set_imaging_save(op, buf, nsteps, first_step))
+
+
+def fdw_gradient_apply(adj, time_m: int, time_M: int, nt: int, imaging: int, first_step: int, nsteps: int,
+                       grad: int, stream: Optional[int] = None):
+    _chk(load().fdw_gradient_apply(adj, time_m, time_M, nt, imaging, first_step, nsteps, grad, stream))
 
 
 def fdw_operator_set_timing(op, enable):

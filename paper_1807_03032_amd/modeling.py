@@ -14,6 +14,12 @@ the residual traces injected at the receivers (inside the damping division),
 with the source-side output sampled from D nu.  The gradient of
 J(m) = sum_t <d(t), rec(t)> is the zero-lag imaging condition
   dJ/dm = -sum_t nu(t+1) [(u(t+1) - 2u(t) + u(t-1))/dt^2 + eta (u(t+1) - u(t-1))/(2 dt)].
+The forward kernels store the bracket (times dt^2) of each step of a segment
+as they compute it, and the adjoint kernels fold the product with nu into
+their own launches, so a segment's gradient is one forward apply (skipped for
+the last segment, whose factors the forward run itself keeps) and one adjoint
+call.  With enough device memory the segment is the whole run and nothing is
+recomputed.
 """
 from __future__ import annotations
 
@@ -29,18 +35,21 @@ class IsoModeling:
     """One isotropic shot geometry on the GPU: forward, adjoint, gradient.
 
     shape/extent/origin follow fdw_grid_create; src_coords [nsrc][ndim],
-    rec_coords [nrec][ndim]; `checkpoint_every` = K levels between checkpoints
-    (each checkpoint keeps two consecutive levels).
+    rec_coords [nrec][ndim]; `checkpoint_every` = K steps between checkpoints
+    (each checkpoint keeps two consecutive levels; the gradient keeps the
+    imaging factors of one K-step segment).  None: K = nt (no recomputation)
+    when the factors of all nt steps fit in `history_fraction` of the free
+    device memory, else 50.
     """
 
     def __init__(self, shape, extent, origin, so: int, dt: float, nt: int, nbl: int, vmax: float, src_coords,
-                 rec_coords, device="cuda:0", checkpoint_every: int = 50, rc: float = 1e-3):
+                 rec_coords, device="cuda:0", checkpoint_every: Optional[int] = 50, rc: float = 1e-3,
+                 history_fraction: float = 0.9):
         import torch
 
         self.torch = torch
         self.dev = torch.device(device)
         self.nt, self.dt, self.so = int(nt), float(dt), int(so)
-        self.K = max(1, int(checkpoint_every))
         self.grid = fdw.fdw_grid_create(shape, extent, origin)
         self.lay = fdw.fdw_field_layout(self.grid, so)
         E = self.lay.elems_per_slot
@@ -76,13 +85,23 @@ class IsoModeling:
 
         self.fwd = fdw.fdw_operator_create(desc(self.u_tf, self.f_src, self.f_rec, fdw.FDW_FORWARD))
         self.adj = fdw.fdw_operator_create(desc(self.nu_tf, self.a_src, self.a_rec, fdw.FDW_ADJOINT))
-        self.ncp = (nt + self.K - 1) // self.K
-        self.cp = None    # checkpoints [ncp][2 slots]: levels (kK - 1, kK)
-        self.hist = None  # levels t0 + 1 .. t0 + K of one segment
         self.grad = alloc(1)
+        if checkpoint_every is None:
+            free, _ = torch.cuda.mem_get_info(self.dev)
+            checkpoint_every = self.nt if self.nt * E * 4 <= history_fraction * free else 50
+        self.K = min(max(1, int(checkpoint_every)), self.nt)
+        self.ncp = (nt + self.K - 1) // self.K
+        # checkpoints [ncp][2 slots]: levels (kK - 1, kK); imaging factors of the
+        # steps t0 .. t0 + K - 1 of one segment.  Allocated (and first touched:
+        # fresh device memory may be cleared on first use) with the model, so
+        # that runs reuse them
+        self.cp = torch.zeros(self.ncp * 2 * E, dtype=torch.float32, device=self.dev)
+        self.hist = torch.zeros(self.K * E, dtype=torch.float32, device=self.dev)
         # changes with every new m and every forward run: the checkpoints (and
         # q) a gradient uses belong to the state of that number
         self.state_id = 0
+        self.hist_seg = None  # (segment, state) whose factors self.hist holds
+        self.cp_state = None  # state the checkpoints belong to
 
     # ------------------------------------------------------------------ data
     def stream(self):
@@ -109,14 +128,22 @@ class IsoModeling:
         self.u.zero_()
         self.rec.zero_()
         fdw.fdw_operator_set_save(self.fwd, None)
-        if checkpoints and self.cp is None:
-            self.cp = torch.zeros(self.ncp * 2 * self.E, dtype=torch.float32, device=self.dev)
+        fdw.fdw_operator_set_imaging_save(self.fwd, None)
+        self.hist_seg = None
         for k in range(self.ncp):
             t0, t1 = k * self.K, min((k + 1) * self.K, self.nt)
+            last = checkpoints and k == self.ncp - 1
             if checkpoints:  # levels t0 - 1 and t0 live in slots (t0 - 1) % 3 and t0 % 3
                 self._slot(self.cp, 2 * k).copy_(self._slot(self.u, (t0 + 2) % 3))
                 self._slot(self.cp, 2 * k + 1).copy_(self._slot(self.u, t0 % 3))
+            if last:  # the gradient starts with this segment: keep its imaging factors now
+                fdw.fdw_operator_set_imaging_save(self.fwd, self.hist.data_ptr(), t1 - t0, t0)
             fdw.fdw_operator_apply(self.fwd, t0, t1 - 1, self.stream())
+            if last:
+                fdw.fdw_operator_set_imaging_save(self.fwd, None)
+                self.hist_seg = (k, self.state_id)
+        if checkpoints:
+            self.cp_state = self.state_id
         return self.rec.clone()
 
     # --------------------------------------------------------------- adjoint
@@ -136,39 +163,29 @@ class IsoModeling:
         forward() (or of q, recomputed with checkpoints).  Returns the logical
         gradient as a tensor."""
         torch = self.torch
-        if q is not None or self.cp is None:
+        if q is not None or self.cp_state != self.state_id:
             self.forward(self.q if q is None else q, checkpoints=True)
         d = torch.as_tensor(d, dtype=torch.float32, device=self.dev).reshape(self.nt, self.nrec)
         self.d_rev.copy_(torch.flip(d, dims=[0]))
         self.nu.zero_()
         self.a_out.zero_()
         self.grad.zero_()
-        if self.hist is None:
-            self.hist = torch.zeros(self.K * self.E, dtype=torch.float32, device=self.dev)
         s = self.stream()
         for k in reversed(range(self.ncp)):
             t0, t1 = k * self.K, min((k + 1) * self.K, self.nt)
-            # recompute the segment: restore levels t0 - 1, t0, save levels t0 + 1 .. t1
-            self._slot(self.u, (t0 + 2) % 3).copy_(self._slot(self.cp, 2 * k))
-            self._slot(self.u, t0 % 3).copy_(self._slot(self.cp, 2 * k + 1))
-            fdw.fdw_operator_set_save(self.fwd, self.hist.data_ptr(), t1 - t0, 1, t0 + 1)
-            fdw.fdw_operator_apply(self.fwd, t0, t1 - 1, s)
-            fdw.fdw_operator_set_save(self.fwd, None)
-
-            def level(L):
-                if L == t0 - 1:
-                    return self._ptr(self.cp, 2 * k)
-                if L == t0:
-                    return self._ptr(self.cp, 2 * k + 1)
-                return self._ptr(self.hist, L - t0 - 1)
-
-            # adjoint steps for t = t1 - 1 .. t0 (tau = nt - 1 - t), imaging after each
-            for t in range(t1 - 1, t0 - 1, -1):
-                tau = self.nt - 1 - t
-                fdw.fdw_operator_apply(self.adj, tau, tau, s)
-                nu_ptr = self._ptr(self.nu, (tau + 1) % 3)  # adjoint level tau + 1 = nu(t + 1)
-                fdw.fdw_gradient_accumulate(self.fwd, nu_ptr, level(t + 1), level(t), level(t - 1),
-                                            self.grad.data_ptr(), s)
+            if self.hist_seg != (k, self.state_id):
+                # recompute the segment from its checkpoint (levels t0 - 1, t0),
+                # keeping the imaging factors of its steps t0 .. t1 - 1
+                self._slot(self.u, (t0 + 2) % 3).copy_(self._slot(self.cp, 2 * k))
+                self._slot(self.u, t0 % 3).copy_(self._slot(self.cp, 2 * k + 1))
+                fdw.fdw_operator_set_imaging_save(self.fwd, self.hist.data_ptr(), t1 - t0, t0)
+                fdw.fdw_operator_apply(self.fwd, t0, t1 - 1, s)
+                fdw.fdw_operator_set_imaging_save(self.fwd, None)
+                self.hist_seg = (k, self.state_id)
+            # adjoint steps tau = nt - t1 .. nt - 1 - t0 (forward steps t1 - 1 .. t0)
+            # with the imaging condition, in one call
+            fdw.fdw_gradient_apply(self.adj, self.nt - t1, self.nt - 1 - t0, self.nt, self.hist.data_ptr(), t0,
+                                   t1 - t0, self.grad.data_ptr(), s)
         return fdw.slot_view(self.grad, self.lay, 0).clone()
 
     def close(self):

@@ -240,3 +240,13 @@ def test_bandwidth_probe_validation(lib):
         with pytest.raises(fdw.FdwError) as e:
             fdw.fdw_bandwidth_probe(kind, dst, a, b, 1.0, n)
         assert e.value.code == fdw.FDW_ERR_ARG, args
+
+
+def test_imaging_entry_points_validate_without_device(lib):
+    """NULL operators and buffers are refused before any device call."""
+    with pytest.raises(fdw.FdwError) as e:
+        fdw.fdw_operator_set_imaging_save(None, 256, 4, 0)
+    assert e.value.code == fdw.FDW_ERR_ARG
+    with pytest.raises(fdw.FdwError) as e:
+        fdw.fdw_gradient_apply(None, 0, 3, 4, 256, 0, 4, 512)
+    assert e.value.code == fdw.FDW_ERR_ARG
