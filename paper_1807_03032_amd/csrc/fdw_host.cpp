@@ -121,6 +121,10 @@ struct fdw_op {
     int64_t *d_src_base = nullptr, *d_rec_base = nullptr;
     float *d_src_w = nullptr, *d_rec_w = nullptr;
     int *d_src_idx = nullptr, *d_rec_idx = nullptr;  // [npoint][3] base grid indices
+    // injection by gather (SparseArgs::ntarget): targets, offsets, lanes
+    int src_ntarget = 0;
+    int64_t *d_src_tgt = nullptr;
+    int *d_src_goff = nullptr, *d_src_glane = nullptr;
     // subsampled level saving
     float *save_buf = nullptr;
     int64_t save_nlevels = 0;
@@ -475,6 +479,12 @@ static void release_device(fdw_op *op) {
     if (op->d_src_idx) (void)hipFree(op->d_src_idx);
     if (op->d_rec_idx) (void)hipFree(op->d_rec_idx);
     op->d_src_idx = op->d_rec_idx = nullptr;
+    if (op->d_src_tgt) (void)hipFree(op->d_src_tgt);
+    if (op->d_src_goff) (void)hipFree(op->d_src_goff);
+    if (op->d_src_glane) (void)hipFree(op->d_src_glane);
+    op->d_src_tgt = nullptr;
+    op->d_src_goff = op->d_src_glane = nullptr;
+    op->src_ntarget = 0;
     for (hipEvent_t e : op->ev_pool) (void)hipEventDestroy(e);
     op->ev_pool.clear();
     for (hipEvent_t e : op->ev_step) (void)hipEventDestroy(e);
@@ -518,6 +528,47 @@ static int upload_sparse(fdw_op *op, const fdw_sparse *s, double scale, int64_t 
         if (e == hipSuccess) e = hipMemcpy(*d_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return fail_hip(e, "operator_create: sparse upload");
     }
+    return FDW_OK;
+}
+
+// Injection of many sparse points as a gather: every lane's target element
+// (corner offsets as the kernels compute them: digit k of c in base r along
+// axis k), sorted by target then lane, grouped per target.
+constexpr int64_t kGatherMinLanes = 4096;
+static int build_inject_gather(fdw_op *op, const fdw_sparse *s) {
+    const int nc = s->ncorner, r = s->r;
+    const int64_t lanes = (int64_t)s->npoint * nc;
+    if (lanes < kGatherMinLanes || lanes > INT32_MAX) return FDW_OK;
+    const int64_t st1 = op->ndim == 3 ? op->geom.sy : op->geom.sz, st2 = op->ndim == 3 ? op->geom.sz : 0;
+    std::vector<std::pair<int64_t, int>> tl((size_t)lanes);
+    for (int p = 0; p < s->npoint; ++p) {
+        const int64_t b = element_offset(op, &s->base[(size_t)p * op->ndim]);
+        for (int c = 0; c < nc; ++c) {
+            const int j0 = c % r, j1 = (c / r) % r, j2 = c / (r * r);
+            tl[(size_t)p * nc + c] = {b + j0 + j1 * st1 + j2 * st2, p * nc + c};
+        }
+    }
+    std::sort(tl.begin(), tl.end());
+    std::vector<int64_t> tgt;
+    std::vector<int> goff, glane((size_t)lanes);
+    for (size_t k = 0; k < tl.size(); ++k) {
+        if (k == 0 || tl[k].first != tl[k - 1].first) {
+            tgt.push_back(tl[k].first);
+            goff.push_back((int)k);
+        }
+        glane[k] = tl[k].second;
+    }
+    goff.push_back((int)lanes);
+    hipError_t e = hipMalloc((void **)&op->d_src_tgt, sizeof(int64_t) * tgt.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&op->d_src_goff, sizeof(int) * goff.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&op->d_src_glane, sizeof(int) * glane.size());
+    if (e != hipSuccess) return fail(FDW_ERR_NOMEM, "operator_create: injection gather: %s", hipGetErrorString(e));
+    e = hipMemcpy(op->d_src_tgt, tgt.data(), sizeof(int64_t) * tgt.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(op->d_src_goff, goff.data(), sizeof(int) * goff.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(op->d_src_glane, glane.data(), sizeof(int) * glane.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail_hip(e, "operator_create: injection gather upload");
+    op->src_ntarget = (int)tgt.size();
     return FDW_OK;
 }
 
@@ -676,6 +727,7 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
     // sparse preprocessing: element offsets and float weights
     if (d.src) {
         st = upload_sparse(op, d.src, d.dt * d.dt, &op->d_src_base, &op->d_src_w, &op->d_src_idx);
+        if (!st) st = build_inject_gather(op, d.src);
         if (!st && d.src->npoint <= kMaxFusedSrc && d.src->r == 2) {
             op->src_fused = true;
             FusedSrc &F = op->fsrc_template;
@@ -852,6 +904,10 @@ static SparseArgs sparse_template(const fdw_op *op, const fdw_sparse *sp, bool r
         a.base = op->d_src_base;
         a.w = op->d_src_w;
         a.m = d.m->d;
+        a.ntarget = op->src_ntarget;
+        a.tgt = op->d_src_tgt;
+        a.goff = op->d_src_goff;
+        a.glane = op->d_src_glane;
     }
     return a;
 }

@@ -96,6 +96,12 @@ struct SparseArgs {
     float *field;                // injection target / interpolation source
     const float *q_row;          // injection: samples of this step
     float *rec_row;              // interpolation: output row of this step
+    // injection by gather (many points): the distinct target elements tgt[j]
+    // and, for each, its lanes (p * ncorner + c, ascending) at
+    // glane[goff[j] .. goff[j + 1]); ntarget = 0: scatter with atomics
+    int ntarget;
+    const int64_t *tgt;
+    const int *goff, *glane;
 };
 
 // One shot of a fused multi-shot launch of the one-thread-per-point kernels.

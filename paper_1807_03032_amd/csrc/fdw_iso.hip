@@ -80,7 +80,10 @@ static IsoShape iso_stream_shape(const Geom &g) {
     // take that shape (8 waves): half the y-halo rows and warm-up planes per
     // point of the 64 x 8 x 32 default (512^3: 451 vs 470 us per step)
     const int64_t cols16 = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
-    if (cols16 * ((g.nz + 63) / 64) >= 2048) sh = IsoShape{2, 64, 2, 8};
+    const int64_t chunks16 = cols16 * ((g.nz + 63) / 64);
+    // (or one round of them fills nine tenths of the 512 eight-wavefront
+    // workgroup slots: 320^3, 500 chunks, 130 vs 134 us per step)
+    if (chunks16 >= 2048 || (chunks16 >= 461 && chunks16 <= 512)) sh = IsoShape{2, 64, 2, 8};
     if (const char *e = std::getenv("FDW_ISO_TILE")) {
         int a = 0, b = 0, c = 1, d = 4;
         const int n = std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d);
@@ -150,7 +153,8 @@ struct IsoImgOpWide : IsoImgOp {
 // still fill nine tenths of the chip's 1024 four-wavefront workgroup slots
 // (it moves 28 bytes per point, 4 of them re-read at chunk ends: 320^3 with
 // 64-plane chunks, 1000 workgroups, 0.32 s per 1500-step gradient against
-// 0.35 s with the forward step's 32).
+// 0.35 s with the forward step's 32; 64 x 16 tiles of eight wavefronts
+// measured no faster).
 static int image_zchunk(const Geom &g) {
     const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
     int zc = 64;
@@ -159,7 +163,7 @@ static int image_zchunk(const Geom &g) {
 }
 
 template <int R>
-static hipError_t launch_iso3d_image(const IsoArgs &a, int zc, hipStream_t s, const LaunchEvents &ev) {
+static hipError_t launch_iso3d_image(const IsoArgs &a, hipStream_t s, const LaunchEvents &ev) {
     IsoImgOp op;
     static_cast<IsoOp &>(op) = make_iso_op(a);
     op.grad = a.grad;
@@ -170,6 +174,7 @@ static hipError_t launch_iso3d_image(const IsoArgs &a, int zc, hipStream_t s, co
     F.p[1] = a.m;
     F.p[2] = a.img_s;
     F.p[3] = a.grad;
+    const int zc = image_zchunk(a.g);
     if constexpr (R <= 4) {
         if (iso_ring_engine(R))
             return launch_stream3d_ring<R, 2, 1, 4>(op, F, a.g, zc, s, ev.start, ev.stop, a.rec);
@@ -187,7 +192,7 @@ static hipError_t launch_iso3d_image(const IsoArgs &a, int zc, hipStream_t s, co
 template <int R>
 static hipError_t launch_iso3d_stream(const IsoArgs &a, hipStream_t s, const LaunchEvents &ev) {
     const IsoShape sh = iso_stream_shape(a.g);
-    if (a.img_s) return launch_iso3d_image<R>(a, image_zchunk(a.g), s, ev);
+    if (a.img_s) return launch_iso3d_image<R>(a, s, ev);
     // FDW_ISO_WIDE=1 takes the wide form on any grid (checks of that path)
     if (iso_wide_form(a.g, R))
         return launch_stream3d<R, 2, 2, 4>(IsoOpWide{make_iso_op(a)}, iso_fields(a), a.g, sh.zc, s, ev.start, ev.stop,

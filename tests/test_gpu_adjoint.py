@@ -55,12 +55,13 @@ def ogrid(prob):
                        rc=prob.rc)
 
 
-@pytest.mark.parametrize("ndim,so", [(3, 8), (2, 4), (3, 4)])
-def test_adjoint_matches_oracle_and_dot_test(dev, ndim, so):
-    prob = problem(ndim, so, 45, 90 + so)
+@pytest.mark.parametrize("ndim,so,nrec", [(3, 8, 9), (2, 4, 9), (3, 4, 9), (3, 8, 700)])
+def test_adjoint_matches_oracle_and_dot_test(dev, ndim, so, nrec):
+    """700 receivers: the residual injection takes the gather kernel."""
+    prob = problem(ndim, so, 45, 90 + so, nrec=nrec)
     rng = np.random.default_rng(7)
     d = rng.standard_normal((prob.nt, prob.rec_coords.shape[0])).astype(np.float32).astype(np.float64)
-    say("adjoint", ndim, so)
+    say("adjoint", ndim, so, nrec)
     md = model_for(prob, dev, 10)
     try:
         fq = md.forward(prob.src).cpu().numpy().astype(np.float64)

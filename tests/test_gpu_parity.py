@@ -443,6 +443,24 @@ def test_ring_engine_fields_above_2gib(torch_dev, monkeypatch):
     np.testing.assert_array_equal(t0, t1)
 
 
+@pytest.mark.parametrize("kind,shape,so,nsrc", [("iso", (40, 36, 30), 8, 600), ("tti", (33, 28, 25), 8, 600),
+                                                ("iso", (70, 55), 4, 1100)])
+def test_many_sources_injected_by_gather(torch_dev, kind, shape, so, nsrc):
+    """4096 or more injection lanes (sources x corners) take the gather
+    kernel (one thread per distinct target element, no atomics); with
+    hundreds of sources on a small grid most targets receive several
+    contributions.  The oracle's results, and the same bits on a second run."""
+    prob = W.small_problem(kind, shape, so, nt=20, seed=95, nsrc=nsrc, nrec=12)
+    say("gather injection", kind, shape, so, nsrc)
+    gf, gtr, _ = gpu_run(prob, torch_dev)
+    of, otr = oracle_run(prob)
+    check(prob, gf, gtr, of, otr)
+    gf2, gtr2, _ = gpu_run(prob, torch_dev)
+    for nm in gf:
+        np.testing.assert_array_equal(gf2[nm][1], gf[nm][1])
+    np.testing.assert_array_equal(gtr2, gtr)
+
+
 @pytest.mark.parametrize("kind,shape,so", [("iso", (37, 29, 23), 8), ("tti", (33, 27, 21), 12), ("iso", (67, 45), 4),
                                            ("tti", (48, 39), 8), ("iso", (70, 41, 9), 16)])
 def test_parameter_halos_are_not_read(torch_dev, kind, shape, so):
