@@ -121,10 +121,12 @@ struct fdw_op {
     int64_t *d_src_base = nullptr, *d_rec_base = nullptr;
     float *d_src_w = nullptr, *d_rec_w = nullptr;
     int *d_src_idx = nullptr, *d_rec_idx = nullptr;  // [npoint][3] base grid indices
-    // injection by gather (SparseArgs::ntarget): targets, offsets, lanes
+    // injection by gather (SparseArgs::ntarget): targets, offsets, lane
+    // points, lane weights, damping divisors
     int src_ntarget = 0;
     int64_t *d_src_tgt = nullptr;
-    int *d_src_goff = nullptr, *d_src_glane = nullptr;
+    int *d_src_goff = nullptr, *d_src_gp = nullptr;
+    float *d_src_gw = nullptr, *d_src_gd = nullptr;
     // subsampled level saving
     float *save_buf = nullptr;
     int64_t save_nlevels = 0;
@@ -481,9 +483,12 @@ static void release_device(fdw_op *op) {
     op->d_src_idx = op->d_rec_idx = nullptr;
     if (op->d_src_tgt) (void)hipFree(op->d_src_tgt);
     if (op->d_src_goff) (void)hipFree(op->d_src_goff);
-    if (op->d_src_glane) (void)hipFree(op->d_src_glane);
+    if (op->d_src_gp) (void)hipFree(op->d_src_gp);
+    if (op->d_src_gw) (void)hipFree(op->d_src_gw);
+    if (op->d_src_gd) (void)hipFree(op->d_src_gd);
     op->d_src_tgt = nullptr;
-    op->d_src_goff = op->d_src_glane = nullptr;
+    op->d_src_goff = op->d_src_gp = nullptr;
+    op->d_src_gw = op->d_src_gd = nullptr;
     op->src_ntarget = 0;
     for (hipEvent_t e : op->ev_pool) (void)hipEventDestroy(e);
     op->ev_pool.clear();
@@ -533,40 +538,61 @@ static int upload_sparse(fdw_op *op, const fdw_sparse *s, double scale, int64_t 
 
 // Injection of many sparse points as a gather: every lane's target element
 // (corner offsets as the kernels compute them: digit k of c in base r along
-// axis k), sorted by target then lane, grouped per target.
+// axis k), sorted by target then lane, grouped per target, with the lane's
+// point and weight (scaled as upload_sparse scales them) and the target's
+// damping divisor 1 + a (the float sum corner_damp forms on the device).
 constexpr int64_t kGatherMinLanes = 4096;
-static int build_inject_gather(fdw_op *op, const fdw_sparse *s) {
+static int build_inject_gather(fdw_op *op, const fdw_sparse *s, double scale, const std::vector<float> &eta) {
     const int nc = s->ncorner, r = s->r;
     const int64_t lanes = (int64_t)s->npoint * nc;
     if (lanes < kGatherMinLanes || lanes > INT32_MAX) return FDW_OK;
     const int64_t st1 = op->ndim == 3 ? op->geom.sy : op->geom.sz, st2 = op->ndim == 3 ? op->geom.sz : 0;
-    std::vector<std::pair<int64_t, int>> tl((size_t)lanes);
+    const int nx = op->geom.nx, ny = op->geom.ny;
+    struct Lane {
+        int64_t tgt;
+        int lane;
+        float d;
+    };
+    std::vector<Lane> tl((size_t)lanes);
     for (int p = 0; p < s->npoint; ++p) {
-        const int64_t b = element_offset(op, &s->base[(size_t)p * op->ndim]);
+        const int64_t *b = &s->base[(size_t)p * op->ndim];
+        const int64_t b0 = element_offset(op, b);
         for (int c = 0; c < nc; ++c) {
             const int j0 = c % r, j1 = (c / r) % r, j2 = c / (r * r);
-            tl[(size_t)p * nc + c] = {b + j0 + j1 * st1 + j2 * st2, p * nc + c};
+            float a;
+            if (op->ndim == 3)
+                a = eta[(size_t)(b[0] + j0)] + eta[(size_t)(nx + b[1] + j1)] + eta[(size_t)(nx + ny + b[2] + j2)];
+            else
+                a = eta[(size_t)(b[0] + j0)] + eta[(size_t)(nx + ny + b[1] + j1)];
+            tl[(size_t)p * nc + c] = {b0 + j0 + j1 * st1 + j2 * st2, p * nc + c, 1.0f + a};
         }
     }
-    std::sort(tl.begin(), tl.end());
+    std::sort(tl.begin(), tl.end(),
+              [](const Lane &x, const Lane &y) { return x.tgt != y.tgt ? x.tgt < y.tgt : x.lane < y.lane; });
     std::vector<int64_t> tgt;
-    std::vector<int> goff, glane((size_t)lanes);
+    std::vector<int> goff, gp((size_t)lanes);
+    std::vector<float> gw((size_t)lanes), gd;
     for (size_t k = 0; k < tl.size(); ++k) {
-        if (k == 0 || tl[k].first != tl[k - 1].first) {
-            tgt.push_back(tl[k].first);
+        if (k == 0 || tl[k].tgt != tl[k - 1].tgt) {
+            tgt.push_back(tl[k].tgt);
             goff.push_back((int)k);
+            gd.push_back(tl[k].d);
         }
-        glane[k] = tl[k].second;
+        gp[k] = tl[k].lane / nc;
+        gw[k] = (float)(scale * s->w[(size_t)tl[k].lane]);
     }
     goff.push_back((int)lanes);
     hipError_t e = hipMalloc((void **)&op->d_src_tgt, sizeof(int64_t) * tgt.size());
     if (e == hipSuccess) e = hipMalloc((void **)&op->d_src_goff, sizeof(int) * goff.size());
-    if (e == hipSuccess) e = hipMalloc((void **)&op->d_src_glane, sizeof(int) * glane.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&op->d_src_gp, sizeof(int) * gp.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&op->d_src_gw, sizeof(float) * gw.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&op->d_src_gd, sizeof(float) * gd.size());
     if (e != hipSuccess) return fail(FDW_ERR_NOMEM, "operator_create: injection gather: %s", hipGetErrorString(e));
     e = hipMemcpy(op->d_src_tgt, tgt.data(), sizeof(int64_t) * tgt.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(op->d_src_goff, goff.data(), sizeof(int) * goff.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(op->d_src_glane, glane.data(), sizeof(int) * glane.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(op->d_src_gp, gp.data(), sizeof(int) * gp.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(op->d_src_gw, gw.data(), sizeof(float) * gw.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(op->d_src_gd, gd.data(), sizeof(float) * gd.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail_hip(e, "operator_create: injection gather upload");
     op->src_ntarget = (int)tgt.size();
     return FDW_OK;
@@ -727,7 +753,7 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out) {
     // sparse preprocessing: element offsets and float weights
     if (d.src) {
         st = upload_sparse(op, d.src, d.dt * d.dt, &op->d_src_base, &op->d_src_w, &op->d_src_idx);
-        if (!st) st = build_inject_gather(op, d.src);
+        if (!st) st = build_inject_gather(op, d.src, d.dt * d.dt, eta);
         if (!st && d.src->npoint <= kMaxFusedSrc && d.src->r == 2) {
             op->src_fused = true;
             FusedSrc &F = op->fsrc_template;
@@ -907,7 +933,9 @@ static SparseArgs sparse_template(const fdw_op *op, const fdw_sparse *sp, bool r
         a.ntarget = op->src_ntarget;
         a.tgt = op->d_src_tgt;
         a.goff = op->d_src_goff;
-        a.glane = op->d_src_glane;
+        a.gp = op->d_src_gp;
+        a.gw = op->d_src_gw;
+        a.gd = op->d_src_gd;
     }
     return a;
 }

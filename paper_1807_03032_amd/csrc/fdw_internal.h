@@ -97,11 +97,14 @@ struct SparseArgs {
     const float *q_row;          // injection: samples of this step
     float *rec_row;              // interpolation: output row of this step
     // injection by gather (many points): the distinct target elements tgt[j]
-    // and, for each, its lanes (p * ncorner + c, ascending) at
-    // glane[goff[j] .. goff[j + 1]); ntarget = 0: scatter with atomics
+    // and, for each, its lanes (ascending p * ncorner + c) at
+    // goff[j] .. goff[j + 1] - 1 of gp (sparse point) and gw (its weight);
+    // gd[j] = 1 + a at the target (adjoint injection); ntarget = 0: scatter
+    // with atomics
     int ntarget;
     const int64_t *tgt;
-    const int *goff, *glane;
+    const int *goff, *gp;
+    const float *gw, *gd;
 };
 
 // One shot of a fused multi-shot launch of the one-thread-per-point kernels.

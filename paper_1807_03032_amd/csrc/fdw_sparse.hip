@@ -48,20 +48,20 @@ __global__ void __launch_bounds__(256) inject_kernel(SparseArgs a) {
 }
 
 // Injection as a gather, one thread per distinct target element: the same
-// per-lane terms as inject_kernel, summed in lane order and added once (no
-// atomics, the same bits on every run).  Taken for many sparse points, where
-// atomics to shared corners serialise (102,400 receivers: 17 -> a few us).
+// per-lane terms as inject_kernel (weights, point indices and the damping
+// divisor gathered per target at operator creation, so that few loads depend
+// on each other), summed in lane order and added once: no atomics, the same
+// bits on every run.  Taken for many sparse points.
 __global__ void __launch_bounds__(256) inject_gather_kernel(SparseArgs a) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.ntarget) return;
     const int64_t i = a.tgt[j];
     const float rm = fast_rcp(a.m[i]);
+    const float d = a.damp_mode == 1 ? a.gd[j] : 1.0f;
     float acc = 0.0f;
     for (int k = a.goff[j]; k < a.goff[j + 1]; ++k) {
-        const int l = a.glane[k];
-        const int p = l / a.ncorner, c = l % a.ncorner;
-        float v = a.w[l] * a.q_row[p] * rm;
-        if (a.damp_mode == 1) v /= 1.0f + corner_damp(a, p, c);
+        float v = a.gw[k] * a.q_row[a.gp[k]] * rm;
+        if (a.damp_mode == 1) v /= d;
         acc += v;
     }
     a.field[i] += acc;
