@@ -210,8 +210,19 @@ int fdw_operator_create(const fdw_op_desc *desc, fdw_op **out);
  * the same result as one apply.  Asynchronous: work is enqueued on `stream`
  * (a hipStream_t; NULL = the null stream) and the call returns; launch errors
  * are reported here, execution errors at the next call or fdw_sync.
+ * Graphs (Section 4.5's loop captured once): when a call repeats the range and
+ * the saving settings of the operator's previous call, its launch sequence is
+ * captured into a hipGraph, which that call and later calls with the same key
+ * replay on a private stream ordered after `stream`'s earlier work and before
+ * its later work (kernel timing on, receiver sampling on a second stream, an
+ * open range (time_M = -1) or FDW_APPLY_GRAPH=0: plain launches).  The
+ * results are the same bits either way.
  * Errors: FDW_ERR_ARG (range), FDW_ERR_DEVICE. */
 int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream);
+
+/* Graphs the operator's applies built and replays launched so far.
+ * Errors: FDW_ERR_ARG (NULL op). */
+int fdw_operator_graph_stats(const fdw_op *op, int64_t *builds, int64_t *replays);
 
 /* Allocation-free variant of fdw_operator_apply, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,

@@ -153,6 +153,14 @@ struct fdw_op {
     bool overlap_interp = false;
     hipStream_t side = nullptr;
     std::vector<hipEvent_t> ev_step, ev_interp;  // ring of nslots + 1 each
+    // apply graph: a range applied a second time with the same settings is
+    // captured then, and replayed on a private stream from then on
+    std::vector<int64_t> graph_key, graph_seen;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    hipEvent_t graph_ev[2] = {nullptr, nullptr};
+    int64_t graph_builds = 0, graph_replays = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -467,7 +475,22 @@ int fdw_sparse_destroy(fdw_sparse *s) {
 // ---------------------------------------------------------------------------
 // Operator construction helpers
 // ---------------------------------------------------------------------------
+static void drop_apply_graph(fdw_op *op) {
+    if (op->graph_exec) (void)hipGraphExecDestroy(op->graph_exec);
+    if (op->graph) (void)hipGraphDestroy(op->graph);
+    op->graph_exec = nullptr;
+    op->graph = nullptr;
+    op->graph_key.clear();
+}
+
 static void release_device(fdw_op *op) {
+    drop_apply_graph(op);
+    for (hipEvent_t &e : op->graph_ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    if (op->graph_stream) (void)hipStreamDestroy(op->graph_stream);
+    op->graph_stream = nullptr;
     if (op->d_eta) (void)hipFree(op->d_eta);
     if (op->d_stage) (void)hipFree(op->d_stage);
     if (op->d_fsrc) (void)hipFree(op->d_fsrc);
@@ -1385,11 +1408,82 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
 }
 
 
+// The launch sequence of an apply depends only on its range and the
+// operator's settings (every buffer is bound at creation, and the kernels read
+// the data, sources included, at run time).  An apply whose range and settings
+// repeat those of the previous call is captured into a hipGraph on a private
+// stream and instantiated; the next calls with that key replay it, ordered
+// after the caller's stream and before its later work by two events.  Not
+// with kernel timing on (events around launches), receiver sampling on a
+// second stream, or FDW_APPLY_GRAPH=0.
+static int apply_graphed(fdw_op *op, int time_m, int time_M, hipStream_t s) {
+    const std::vector<int64_t> key = {time_m,
+                                      time_M,
+                                      (int64_t)(intptr_t)op->save_buf,
+                                      op->save_nlevels,
+                                      op->save_every,
+                                      op->save_first,
+                                      (int64_t)(intptr_t)op->isave_buf,
+                                      op->isave_n,
+                                      op->isave_first};
+    if (!(op->graph_exec && key == op->graph_key)) {
+        if (key != op->graph_seen) {  // first time: launch directly
+            op->graph_seen = key;
+            return apply_impl(op, time_m, time_M, s, op->d_stage, false);
+        }
+        drop_apply_graph(op);
+        hipError_t e = hipSuccess;
+        if (!op->graph_stream) e = hipStreamCreateWithFlags(&op->graph_stream, hipStreamNonBlocking);
+        for (hipEvent_t &ev : op->graph_ev)
+            if (e == hipSuccess && !ev) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return fail_hip(e, "operator_apply: graph stream");
+        e = hipStreamBeginCapture(op->graph_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail_hip(e, "operator_apply: hipStreamBeginCapture");
+        const int st = apply_impl(op, time_m, time_M, op->graph_stream, op->d_stage, false);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(op->graph_stream, &g);
+        if (st != FDW_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != FDW_OK ? st : fail_hip(e, "operator_apply: graph capture");
+        }
+        e = hipGraphInstantiate(&op->graph_exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            op->graph_exec = nullptr;
+            return fail_hip(e, "operator_apply: hipGraphInstantiate");
+        }
+        op->graph = g;
+        op->graph_key = key;
+        op->graph_builds++;
+    }
+    hipError_t e = hipEventRecord(op->graph_ev[0], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(op->graph_stream, op->graph_ev[0], 0);
+    if (e == hipSuccess) e = hipGraphLaunch(op->graph_exec, op->graph_stream);
+    if (e == hipSuccess) e = hipEventRecord(op->graph_ev[1], op->graph_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, op->graph_ev[1], 0);
+    if (e != hipSuccess) return fail_hip(e, "operator_apply: graph replay");
+    op->graph_replays++;
+    return FDW_OK;
+}
+
 int fdw_operator_apply(fdw_op *op, int time_m, int time_M, void *stream) {
     FDW_GUARD_BEGIN
     if (!op) return fail(FDW_ERR_ARG, "operator_apply: NULL op");
+    static const bool graphs = [] {
+        const char *e = std::getenv("FDW_APPLY_GRAPH");
+        return !(e && e[0] == '0');
+    }();
+    if (graphs && !op->timing && !op->overlap_interp && time_m >= 0 && time_M >= time_m)
+        return apply_graphed(op, time_m, time_M, (hipStream_t)stream);
     return apply_impl(op, time_m, time_M, stream, op->d_stage, true);
     FDW_GUARD_END
+}
+
+int fdw_operator_graph_stats(const fdw_op *op, int64_t *builds, int64_t *replays) {
+    if (!op) return fail(FDW_ERR_ARG, "graph_stats: NULL op");
+    if (builds) *builds = op->graph_builds;
+    if (replays) *replays = op->graph_replays;
+    return FDW_OK;
 }
 
 int fdw_operator_set_save(fdw_op *op, float *buf, int64_t nlevels, int every, int first_level) {

@@ -44,7 +44,7 @@ EXPORTS = (
     "fdw_sparse_bind_precomputed", "fdw_batch_create", "fdw_batch_apply", "fdw_batch_stats", "fdw_batch_destroy",
     "fdw_server_create", "fdw_server_footprint", "fdw_server_submit", "fdw_server_progress", "fdw_server_info",
     "fdw_server_fetch", "fdw_server_release", "fdw_server_stats", "fdw_server_destroy", "fdw_bandwidth_probe",
-    "fdw_operator_apply_noalloc", "fdw_operator_set_imaging_save", "fdw_gradient_apply",
+    "fdw_operator_apply_noalloc", "fdw_operator_set_imaging_save", "fdw_gradient_apply", "fdw_operator_graph_stats",
 )
 FDW_SHOT_QUEUED, FDW_SHOT_RUNNING, FDW_SHOT_DONE, FDW_SHOT_FAILED = 0, 1, 2, 3
 
@@ -131,6 +131,7 @@ def load(path: str = LIB_PATH):
         "fdw_operator_set_save": (i32, [vp, vp, i64, i32, i32]),
         "fdw_gradient_accumulate": (i32, [vp, vp, vp, vp, vp, vp, vp]),
         "fdw_operator_set_imaging_save": (i32, [vp, vp, i64, i32]),
+        "fdw_operator_graph_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "fdw_gradient_apply": (i32, [vp, i32, i32, i32, vp, i32, i64, vp, vp]),
         "fdw_batch_create": (i32, [pvp]),
         "fdw_batch_apply": (i32, [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]),
@@ -281,6 +282,13 @@ def fdw_operator_set_save(op, buf: Optional[int], nlevels: int = 0, every: int =
 def fdw_gradient_accumulate(op, nu: int, u_next: int, u_cur: int, u_prev: int, grad: int,
                             stream: Optional[int] = None):
     _chk(load().fdw_gradient_accumulate(op, nu, u_next, u_cur, u_prev, grad, stream))
+
+
+def fdw_operator_graph_stats(op):
+    """(graphs built, graph replays) of the operator's applies."""
+    b, r = ctypes.c_int64(0), ctypes.c_int64(0)
+    _chk(load().fdw_operator_graph_stats(op, ctypes.byref(b), ctypes.byref(r)))
+    return b.value, r.value
 
 
 def fdw_operator_set_imaging_save(op, buf: Optional[int], nsteps: int = 0, first_step: int = 0):
