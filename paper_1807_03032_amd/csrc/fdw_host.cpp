@@ -651,8 +651,12 @@ static void pick_variants(fdw_op *op) {
     op->iso_v = naive || big_plane ? IsoVariant::Naive : IsoVariant::Stream;
     op->tti_v = naive || big_plane ? TtiVariant::Naive : TtiVariant::Stream;
     // the persistent kernel handles linear (2 x 2) sparse supports only
+    // (FDW_PERSIST2D=0 keeps small 2D grids on the per-step kernels: checks of that path)
+    const char *p2 = std::getenv("FDW_PERSIST2D");
+    const bool persist_off = p2 && p2[0] == '0';
     const bool linear = (!op->d.src || op->d.src->r == 2) && (!op->d.rec || op->d.rec->r == 2);
-    op->use_persist2d = !naive && linear && op->d.kind == FDW_ISO && op->ndim == 2 && op->d.mode == FDW_FORWARD &&
+    op->use_persist2d = !naive && !persist_off && linear && op->d.kind == FDW_ISO && op->ndim == 2 &&
+                        op->d.mode == FDW_FORWARD &&
                         (int64_t)op->geom.nx * op->geom.nz * (int64_t)sizeof(float) <= kPersist2DMaxLds;
 }
 

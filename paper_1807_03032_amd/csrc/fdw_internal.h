@@ -239,6 +239,10 @@ const char *tb3d_kernel_name(const Geom &g, int R);
 // Launchers (fdw_iso.hip, fdw_tti.hip, fdw_sparse.hip).  Each returns the
 // hipError_t of its launch.
 hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream_t s, const LaunchEvents &ev);
+// 2D step on the ring engine's flat mode (fdw_iso2d_stream.hip): the same
+// bits as the one-thread-per-point 2D kernel; its z-chunk
+hipError_t launch_iso2d_stream(int R, const IsoArgs &a, hipStream_t s, const LaunchEvents &ev);
+int iso2d_stream_zchunk(const Geom &g);
 hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s, const LaunchEvents &ev);
 hipError_t launch_inject(const SparseArgs &a, hipStream_t s);
 hipError_t launch_interp(const SparseArgs &a, hipStream_t s);

@@ -213,6 +213,9 @@ hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream
 #define ISO_S3(r) launch_iso3d_stream<r>(a, s, ev)
     if (ndim == 3 && v == IsoVariant::Stream) { FDW_DISPATCH_R(R, ISO_S3) }
 #undef ISO_S3
+    // (order 16 stays one thread per point: there the ring kernel would copy
+    // its operator record to scratch memory)
+    if (ndim == 2 && v == IsoVariant::Stream && R < 8) return launch_iso2d_stream(R, a, s, ev);
 #define ISO_N3(r) launch_iso_naive<3, r>(a, s, ev)
 #define ISO_N2(r) launch_iso_naive<2, r>(a, s, ev)
     if (ndim == 3) { FDW_DISPATCH_R(R, ISO_N3) }
@@ -298,6 +301,12 @@ const char *iso_kernel_name(int ndim, int R, IsoVariant v, const Geom &g) {
             std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x%d (%d waves) zchunk=%d prefetch=%d", sh.by * sh.ny,
                           sh.by, sh.zc, sh.pf);
         return buf;
+    }
+    if (ndim == 2 && v == IsoVariant::Stream && R < 8) {
+        static thread_local char buf2[64];
+        std::snprintf(buf2, sizeof(buf2), "iso2d_stream 64-column wavefronts zchunk=%d prefetch=2",
+                      iso2d_stream_zchunk(g));
+        return buf2;
     }
     return ndim == 3 ? "iso_naive<3>" : "iso_naive<2>";
 }

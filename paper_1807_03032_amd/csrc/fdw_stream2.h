@@ -37,6 +37,14 @@ __device__ __forceinline__ void static_for(F &&f) {
     static_for_seq(f, std::make_integer_sequence<int, N>{});
 }
 
+// Operators of 2D grids declare kFlatY: the engine then keeps no y halo (the
+// tile is one row of 64 x-columns per wavefront, y = 0 only) and the operator
+// reads no y neighbours.
+template <class Op, class = void>
+struct flat_y : std::false_type {};
+template <class Op>
+struct flat_y<Op, std::void_t<decltype(Op::kFlatY)>> : std::integral_constant<bool, Op::kFlatY> {};
+
 // Ring length: 2R + 1 + PF rounded up to a multiple of PF + 1 (pointwise
 // rings) and of 2 (LDS double buffer).
 constexpr int ring_len(int R, int PF) {
@@ -82,9 +90,12 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
         for (int l = (bid - nb_stencil) * NT + (int)threadIdx.x; l < lanes; l += stride) interp_lane(sp, l);
         return;
     }
-    constexpr int TX = 64, TY = BY * NY, LW = (TX + 2 * R + 63) / 64 * 64, LH = TY + 2 * R;
+    constexpr bool FLAT = flat_y<Op>::value;
+    constexpr int RY = FLAT ? 0 : R;  // y-halo rows above the tile in LDS
+    constexpr int TX = 64, TY = BY * NY, LW = (TX + 2 * R + 63) / 64 * 64, LH = TY + 2 * RY;
     constexpr int RING = ring_len(R, PF), PR = PF + 1;
-    constexpr int NHY = (2 * R + BY - 1) / BY;
+    constexpr int NHY = FLAT ? 0 : (2 * R + BY - 1) / BY;
+    constexpr int NHYA = NHY > 0 ? NHY : 1;  // array extent
     constexpr int NHX = (TY * 2 * R + NT - 1) / NT;
     __shared__ float lds[2][NQ][LH][LW];
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
@@ -118,9 +129,9 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
     float colv[NY];
 #pragma unroll
     for (int j = 0; j < NY; ++j) colv[j] = in[j] ? op.begin_column(x, yb + j) : 0.0f;
-    bool hy_act[NHY];
-    int hy_lds[NHY];
-    uint32_t hy_vb[NHY];
+    bool hy_act[NHYA];
+    int hy_lds[NHYA];
+    uint32_t hy_vb[NHYA];
 #pragma unroll
     for (int i = 0; i < NHY; ++i) {
         const int hr = wy + BY * i;
@@ -138,7 +149,7 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
         hx_act[i] = xi < TY * 2 * R;
         const int hx_r = xi / (2 * R), hx_c = xi % (2 * R);
         const int hx_x = hx_c < R ? x0 - R + hx_c : x0 + TX + (hx_c - R);
-        hx_lrow[i] = R + hx_r;
+        hx_lrow[i] = RY + hx_r;
         hx_lcol[i] = hx_c < R ? hx_c : R + TX + (hx_c - R);
         hx_vb[i] = hx_act[i] ? vbyte(hx_x, y0 + hx_r) : kBufOut;
     }
@@ -151,7 +162,7 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
         // plane j of the walk (z = zs + DIR j) lives in ring slot (j + R) % RING
         float q[NQ][NY][RING];
         float pw[NP][NY][PR];
-        float hy[NQ][NHY][PR], hx[NQ][NHX][PR];
+        float hy[NQ][NHYA][PR], hx[NQ][NHX][PR];
         float pv[PR];
         // stencil-field plane j into its ring slot S (zero outside the domain)
         auto load_head = [&](int j, auto slot_tag) __attribute__((always_inline)) {
@@ -214,7 +225,7 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
 #pragma unroll
                         for (int f = 0; f < NQ; ++f)
 #pragma unroll
-                            for (int c = 0; c < NY; ++c) lds[buf][f][R + wy * NY + c][R + lane] = q[f][c][cs];
+                            for (int c = 0; c < NY; ++c) lds[buf][f][RY + wy * NY + c][R + lane] = q[f][c][cs];
 #pragma unroll
                         for (int h = 0; h < NHY; ++h)
                             if (hy_act[h])
@@ -237,7 +248,7 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
 #pragma unroll
                         for (int c = 0; c < NY; ++c) {
                             RingPoint<R, NQ, NP, NY, LH, LW, RING, PR> pt{
-                                q, lds[buf], pw, c, R + wy * NY + c, R + lane, x, yb + c, z, cs, cp, DIR, so,
+                                q, lds[buf], pw, c, RY + wy * NY + c, R + lane, x, yb + c, z, cs, cp, DIR, so,
                                 vcol[c], cbase};
                             op.template point<R>(pt, tile_flag, colv[c] + plane_val, true);
                         }
