@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfdw.so")
-SOURCES = ["fdw_host.cpp", "fdw_serve.cpp", "fdw_iso.hip", "fdw_iso3d_tb.hip", "fdw_iso2d.hip", "fdw_iso2d_halo.hip", "fdw_iso2d_nohalo.hip", "fdw_iso2d_stream.hip", "fdw_tti.hip", "fdw_sparse.hip", "fdw_util.hip", "fdw_scratch.hip"]
+SOURCES = ["fdw_host.cpp", "fdw_serve.cpp", "fdw_iso.hip", "fdw_iso3d_tb.hip", "fdw_iso2d.hip", "fdw_iso2d_halo.hip", "fdw_iso2d_nohalo.hip", "fdw_iso2d_stream.hip", "fdw_tti.hip", "fdw_tti2d_stream.hip", "fdw_sparse.hip", "fdw_util.hip", "fdw_scratch.hip"]
 
 # Packed-FP32 VALU forms stay disabled: ordinary float code is compiled to
 # scalar-lane v_fma_f32 / v_add_f32 only.

@@ -49,6 +49,18 @@ __device__ __forceinline__ float leapfrog(float u, float u_prev, float cl, float
     return __builtin_fmaf(__builtin_fmaf(1.0f - a, d, cl), __builtin_amdgcn_rcpf(1.0f + a), u);
 }
 
+// Coupled TTI update of p and r from A = L p - H p, B = H r (one rounding
+// pattern for every TTI kernel):
+//   p+ from (1 + 2 eps) A + sqrt(1 + 2 delta) B,  r+ from sqrt(1 + 2 delta) A + B
+__device__ __forceinline__ void tti_update(float pc, float pp, float rc, float rp, float A, float B, float m, float eps,
+                                           float delta, float dt2, float a, float &pn, float &rn) {
+#pragma clang fp contract(off)
+    const float sd = __builtin_sqrtf(__builtin_fmaf(2.0f, delta, 1.0f));
+    const float cdt = dt2 * fast_rcp(m);
+    pn = leapfrog(pc, pp, cdt * __builtin_fmaf(__builtin_fmaf(2.0f, eps, 1.0f), A, sd * B), a);
+    rn = leapfrog(rc, rp, cdt * __builtin_fmaf(sd, A, B), a);
+}
+
 // One pair term of the difference-form Laplacian: acc + w ((a + b) - 2u).
 __device__ __forceinline__ float lap_term(float acc, float w, float a, float b, float u) {
 #pragma clang fp contract(off)

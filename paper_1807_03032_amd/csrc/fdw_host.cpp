@@ -1628,7 +1628,7 @@ int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_b
                               : op->use_tb2d    ? tbname
                               : op->use_tb3d    ? tb3d_kernel_name(op->geom, op->R)
                                                 : iso_kernel_name(op->ndim, op->R, op->iso_v, op->geom))
-                           : tti_kernel_name(op->ndim, op->tti_v, op->geom);
+                           : tti_kernel_name(op->ndim, op->R, op->tti_v, op->geom);
     snprintf(buf, (size_t)buflen, "%s so=%d R=%d ndim=%d src=%s nsrc=%d nrec=%d", name, op->d.space_order, op->R,
              op->ndim, op->src_fused ? "fused" : "kernel", op->d.src ? op->d.src->npoint : 0,
              op->d.rec ? op->d.rec->npoint : 0);

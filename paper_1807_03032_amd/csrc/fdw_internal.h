@@ -243,6 +243,10 @@ hipError_t launch_iso(int ndim, int R, IsoVariant v, const IsoArgs &a, hipStream
 // bits as the one-thread-per-point 2D kernel; its z-chunk
 hipError_t launch_iso2d_stream(int R, const IsoArgs &a, hipStream_t s, const LaunchEvents &ev);
 int iso2d_stream_zchunk(const Geom &g);
+// TTI 2D stages on the same mode (fdw_tti2d_stream.hip): the same bits as the
+// one-thread-per-point 2D stages; their z-chunk
+hipError_t launch_tti2d_stream(int R, const TtiArgs &a, hipStream_t s, const LaunchEvents &ev);
+int tti2d_stream_zchunk(const Geom &g);
 hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s, const LaunchEvents &ev);
 hipError_t launch_inject(const SparseArgs &a, hipStream_t s);
 hipError_t launch_interp(const SparseArgs &a, hipStream_t s);
@@ -302,6 +306,6 @@ hipError_t launch_bandwidth_probe(int kind, float *dst, const float *a, const fl
 
 // Human-readable description of the launch plan of the dominant kernel.
 const char *iso_kernel_name(int ndim, int R, IsoVariant v, const Geom &g);
-const char *tti_kernel_name(int ndim, TtiVariant v, const Geom &g);
+const char *tti_kernel_name(int ndim, int R, TtiVariant v, const Geom &g);
 
 }  // namespace fdw

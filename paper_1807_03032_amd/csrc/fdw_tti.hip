@@ -8,6 +8,8 @@
 
 namespace fdw {
 
+constexpr int kTti2DStreamMaxR = 8;
+
 // Unit normal of the TTI symmetry axis: (sin th cos ph, sin th sin ph, cos th)
 // in 3D, (sin th, cos th) over (x, z) in 2D.
 template <int NDIM>
@@ -25,18 +27,6 @@ __device__ __forceinline__ void tti_normal(const TtiArgs &a, int64_t i, float &n
         ny = 0.0f;
         nz = ct;
     }
-}
-
-// Coupled update of p and r from A = L p - H p, B = H r (one rounding
-// pattern for every TTI kernel):
-//   p+ from (1 + 2 eps) A + sqrt(1 + 2 delta) B,  r+ from sqrt(1 + 2 delta) A + B
-__device__ __forceinline__ void tti_update(float pc, float pp, float rc, float rp, float A, float B, float m, float eps,
-                                           float delta, float dt2, float a, float &pn, float &rn) {
-#pragma clang fp contract(off)
-    const float sd = __builtin_sqrtf(__builtin_fmaf(2.0f, delta, 1.0f));
-    const float cdt = dt2 * fast_rcp(m);
-    pn = leapfrog(pc, pp, cdt * __builtin_fmaf(__builtin_fmaf(2.0f, eps, 1.0f), A, sd * B), a);
-    rn = leapfrog(rc, rp, cdt * __builtin_fmaf(sd, A, B), a);
 }
 
 // n . grad f at element i (centred first derivatives of order 2R).
@@ -392,10 +382,15 @@ hipError_t launch_tti_multi(int ndim, int R, const Geom &g, const void *recs1, c
 #undef TTI_M
 }
 
+// orders whose 2D stages run on the flat ring engine (the others would copy
+// their operator record to scratch memory there)
+static bool tti2d_stream_order(int R) { return R <= kTti2DStreamMaxR; }
+
 hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {
 #define TTI_S3(r) launch_tti3d_stream<r>(a, s, ev)
     if (ndim == 3 && v == TtiVariant::Stream) { FDW_DISPATCH_R(R, TTI_S3) }
 #undef TTI_S3
+    if (ndim == 2 && v == TtiVariant::Stream && tti2d_stream_order(R)) return launch_tti2d_stream(R, a, s, ev);
 #define TTI_N3(r) launch_tti_naive<3, r>(a, s, ev)
 #define TTI_N2(r) launch_tti_naive<2, r>(a, s, ev)
     if (ndim == 3) { FDW_DISPATCH_R(R, TTI_N3) }
@@ -403,7 +398,12 @@ hipError_t launch_tti(int ndim, int R, TtiVariant v, const TtiArgs &a, hipStream
 #undef TTI_N3
 #undef TTI_N2
 }
-const char *tti_kernel_name(int ndim, TtiVariant v, const Geom &g) {
+const char *tti_kernel_name(int ndim, int R, TtiVariant v, const Geom &g) {
+    if (ndim == 2 && v == TtiVariant::Stream && tti2d_stream_order(R)) {
+        static thread_local char buf2[80];
+        std::snprintf(buf2, sizeof(buf2), "tti2d_stream 64-column wavefronts zchunk=%d", tti2d_stream_zchunk(g));
+        return buf2;
+    }
     if (ndim == 3 && v == TtiVariant::Stream) {
         static thread_local char buf[96];
         const TtiShape sh = tti_stream_shape(g);

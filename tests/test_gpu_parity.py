@@ -305,20 +305,24 @@ def test_large_2d_grid_uses_per_step_kernel(torch_dev):
     check(prob, gf, gtr, of, otr)
 
 
-@pytest.mark.parametrize("shape,so", [((401, 301), 4), ((130, 77), 12), ((257, 190), 14), ((70, 33), 8), ((97, 300), 2)])
-def test_2d_tiles_equal_one_thread_per_point(torch_dev, monkeypatch, shape, so):
+@pytest.mark.parametrize("kind,shape,so", [("iso", (401, 301), 4), ("iso", (130, 77), 12), ("iso", (257, 190), 14),
+                                           ("iso", (70, 33), 8), ("iso", (97, 300), 2), ("tti", (401, 301), 4),
+                                           ("tti", (130, 77), 12), ("tti", (203, 150), 16), ("tti", (70, 33), 8)])
+def test_2d_streaming_equals_one_thread_per_point(torch_dev, monkeypatch, kind, shape, so):
     """2D grids too large for the LDS-resident kernel (or with it switched
-    off) run on the ring engine's flat mode, 64-column wavefronts streaming
-    along z (ragged edges here): the oracle's results, and the bits of the
-    one-thread-per-point kernel (FDW_KERNEL=naive)."""
+    off; TTI always) run on the ring engine's flat mode, 64-column wavefronts
+    streaming along z (ragged edges here; TTI angles over a full turn): the
+    oracle's results, and the bits of the one-thread-per-point kernels
+    (FDW_KERNEL=naive)."""
     src = np.array([[10.0 * (shape[0] // 3) + 3.3, 10.0 * (shape[1] // 2) - 4.1], [5.0, 10.0 * (shape[1] - 1)]])
     # receivers on the row of the first source (the wave reaches them in 40 steps)
     rec = np.array([[10.0 * k * (shape[0] - 1) / 11.0, 10.0 * (shape[1] // 2) + 13.7] for k in range(12)])
-    prob = W.small_problem("iso", shape, so, nt=40, seed=34, src_at=src, rec_coords=rec, nbl=6)
-    say("2d tiles", shape, so)
+    prob = W.small_problem(kind, shape, so, nt=40, seed=34, src_at=src, rec_coords=rec, nbl=6,
+                           angle_range=(0.0, 2.0 * np.pi))
+    say("2d streaming", kind, shape, so)
     monkeypatch.setenv("FDW_PERSIST2D", "0")
     gf, gtr, desc = gpu_run(prob, torch_dev)
-    assert "iso2d_stream" in desc, desc
+    assert f"{kind}2d_stream" in desc, desc
     monkeypatch.setenv("FDW_KERNEL", "naive")
     nf, ntr, ndesc = gpu_run(prob, torch_dev)
     assert "naive" in ndesc, ndesc
