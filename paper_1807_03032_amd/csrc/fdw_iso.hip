@@ -85,6 +85,12 @@ static IsoShape iso_stream_shape(const Geom &g) {
     // workgroup slots: 320^3, 500 chunks, 129.5 vs 132.8 us per step with
     // the imaging factor stored)
     if (chunks16 >= 2048 || (chunks16 >= 461 && chunks16 <= 512)) sh = IsoShape{2, 64, 2, 8};
+    // the chunks a walk needs, evened out (400 planes: 13 of 31 rather than
+    // 12 of 32 and one of 16; grids that are multiples of the chunk keep it)
+    if (sh.zc < g.nz) {
+        const int n = (g.nz + sh.zc - 1) / sh.zc;
+        sh.zc = (g.nz + n - 1) / n;
+    }
     if (const char *e = std::getenv("FDW_ISO_TILE")) {
         int a = 0, b = 0, c = 1, d = 4;
         const int n = std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d);

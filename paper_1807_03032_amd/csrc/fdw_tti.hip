@@ -234,19 +234,29 @@ struct TtiShape {
 };
 
 // z-chunk of both stages: 64 for large grids, shorter when stage 2's 64 x 8
-// tile columns are too few to occupy the chip
+// tile columns are too few to occupy the chip; then evened out over the
+// chunks the walk needs (400 planes: 7 chunks of 58 instead of six of 64 and
+// one of 16, whose workgroups ran alone at the end: 1348 -> 1289 us per step
+// at space order 12)
 static int tti_default_zchunk(const Geom &g) {
     const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
-    return adaptive_zchunk(cols, g.nz, 64, 2048, 2048);
+    const int zc = adaptive_zchunk(cols, g.nz, 64, 2048, 2048);
+    const int n = (g.nz + zc - 1) / zc;
+    return (g.nz + n - 1) / n;
 }
 
-static TtiShape tti_stream_shape(const Geom &g) {
+// Stage 1 64 x 16 (two columns per thread), stage 2 64 x 8; at space order 16
+// on grids long enough for 32-plane chunks stage 2 takes 64 x 16 too (fewer
+// halo rows per point: 400^3 1705 -> 1601 us per step, 512^3 3041 -> 2826;
+// equal at 300^3, slower at order 12 and on small grids).
+static TtiShape tti_stream_shape(const Geom &g, int R) {
     TtiShape sh{2, 8, 1, 8, tti_default_zchunk(g)};
+    if (R == 8 && sh.zc >= 32) sh.ny2 = 2;
     if (const char *e = std::getenv("FDW_TTI_TILE")) {
         int a = 0, b = 0, c = 0, d = 0, z = 0;
         if (std::sscanf(e, "%d,%d,%d,%d,%d", &a, &b, &c, &d, &z) == 5 && (a == 1 || a == 2) && (b == 4 || b == 8) &&
-            (c == 1 || c == 2) && (d == 4 || d == 8) && z > 0)
-            sh = TtiShape{a, b, c, d, z};
+            (c == 1 || c == 2) && (d == 4 || d == 8) && z >= 0)
+            sh = TtiShape{a, b, c, d, z > 0 ? z : sh.zc};  // z = 0: the default z-chunk
     }
     if (sh.zc > g.nz) sh.zc = g.nz;
     return sh;
@@ -263,13 +273,13 @@ static hipError_t launch_tti_stage(const Op &op, const StreamFields<NQ, NP> &F, 
     return launch_stream3d<R, NY, tti_prefetch(R, NQ, NY, BY), BY>(op, F, g, zc, s, e0, e1, sp);
 }
 
-// Tuning variants are instantiated for R = 6 (space order 12) only; other
-// orders use (NY, BY) = (2, 8) for stage 1 and (1, 8) for stage 2.
+// Tuning variants are instantiated for R = 6 and 8 (space orders 12 and 16);
+// other orders use (NY, BY) = (2, 8) for stage 1 and (1, 8) for stage 2.
 template <int R, class Op, int NQ, int NP>
 static hipError_t launch_tti_stage_shape(int ny, int by, const Op &op, const StreamFields<NQ, NP> &F, const Geom &g,
                                          int zc, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
                                          const SparseArgs *sp = nullptr) {
-    if constexpr (R == 6) {
+    if constexpr (R == 6 || R == 8) {
         if (ny == 2)
             return by == 8 ? launch_tti_stage<R, 2, 8>(op, F, g, zc, s, e0, e1, sp)
                            : launch_tti_stage<R, 2, 4>(op, F, g, zc, s, e0, e1, sp);
@@ -309,7 +319,7 @@ static void tti_stage2_parts(const TtiArgs &a, TtiS2Op &o2, StreamFields<3, 8> &
 
 template <int R>
 static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {
-    const TtiShape sh = tti_stream_shape(a.g);
+    const TtiShape sh = tti_stream_shape(a.g, R);
     TtiS1Op o1;
     StreamFields<2, 2> F1;
     tti_stage1_parts(a, o1, F1);
@@ -406,7 +416,7 @@ const char *tti_kernel_name(int ndim, int R, TtiVariant v, const Geom &g) {
     }
     if (ndim == 3 && v == TtiVariant::Stream) {
         static thread_local char buf[96];
-        const TtiShape sh = tti_stream_shape(g);
+        const TtiShape sh = tti_stream_shape(g, R);
         std::snprintf(buf, sizeof(buf), "tti3d_stream stage1 tile=64x%d stage2 tile=64x%d zchunk=%d", sh.by1 * sh.ny1,
                       sh.by2 * sh.ny2, sh.zc);
         return buf;
