@@ -967,6 +967,14 @@ static SparseArgs sparse_template(const fdw_op *op, const fdw_sparse *sp, bool r
     return a;
 }
 
+// Does the operator sample its receivers inside its 3D streaming launches
+// (extra workgroups reading the level the launch only reads)?
+static bool samples_in_launch(const fdw_op *op) {
+    const fdw_sparse *r = op->d.rec;
+    return r && r->npoint > 0 && op->ndim == 3 && !op->overlap_interp && r->r == 2 &&
+           (op->d.kind == FDW_ISO ? op->iso_v == IsoVariant::Stream : op->tti_v == TtiVariant::Stream);
+}
+
 // Stencil arguments of step t (level t + 1 from levels t and t - 1; level k
 // in slot k mod nslots, so with two slots the new level overwrites t - 1).
 static void iso_step_args(const fdw_op *op, int t, IsoArgs &a) {
@@ -992,6 +1000,7 @@ static void iso_step_args(const fdw_op *op, int t, IsoArgs &a) {
     a.adjoint = d.mode == FDW_ADJOINT;
     a.save = nullptr;
     a.rec = nullptr;
+    a.sampling = samples_in_launch(op) ? 1 : 0;
 }
 
 static void tti_step_args(const fdw_op *op, int t, TtiArgs &a, float *stage) {
@@ -1627,7 +1636,8 @@ int fdw_operator_describe(const fdw_op *op, char *buf, int buflen, double *alg_b
     const char *name = iso ? (op->use_persist2d ? "iso2d_persistent (LDS-resident, one launch per apply)"
                               : op->use_tb2d    ? tbname
                               : op->use_tb3d    ? tb3d_kernel_name(op->geom, op->R)
-                                                : iso_kernel_name(op->ndim, op->R, op->iso_v, op->geom))
+                                                : iso_kernel_name(op->ndim, op->R, op->iso_v, op->geom,
+                                                                  samples_in_launch(op)))
                            : tti_kernel_name(op->ndim, op->R, op->tti_v, op->geom);
     snprintf(buf, (size_t)buflen, "%s so=%d R=%d ndim=%d src=%s nsrc=%d nrec=%d", name, op->d.space_order, op->R,
              op->ndim, op->src_fused ? "fused" : "kernel", op->d.src ? op->d.src->npoint : 0,

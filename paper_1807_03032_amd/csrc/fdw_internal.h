@@ -57,6 +57,7 @@ struct IsoArgs {
     int adjoint;   // 1: injected terms are divided by the damping factor (1 + a)
     float *save;   // optional: the new level is also stored here (same layout)
     float *isave;  // optional: the step's imaging factor is stored here (3D streaming kernels)
+    int sampling;  // the operator samples its receivers inside its 3D streaming launches
     // optional (3D streaming kernels): imaging condition of the centre level,
     // grad -= u_cur img_s / dt^2
     const float *img_s;
@@ -305,7 +306,7 @@ hipError_t launch_bandwidth_probe(int kind, float *dst, const float *a, const fl
                                   hipStream_t st);
 
 // Human-readable description of the launch plan of the dominant kernel.
-const char *iso_kernel_name(int ndim, int R, IsoVariant v, const Geom &g);
+const char *iso_kernel_name(int ndim, int R, IsoVariant v, const Geom &g, bool sampling);
 const char *tti_kernel_name(int ndim, int R, TtiVariant v, const Geom &g);
 
 }  // namespace fdw

@@ -74,8 +74,17 @@ static int iso_default_zchunk(const Geom &g) {
     return adaptive_zchunk(cols, g.nz, 32, 1024, 2048);
 }
 
-static IsoShape iso_stream_shape(const Geom &g) {
+// sampling: receivers are sampled by extra workgroups of the launch, which
+// the hardware dispatches after the stencil workgroups; chunks that give two
+// rounds of stencil workgroups (2048 rather than 1024) let them overlap the
+// second round (256^3 with 65,536 receivers: 50.2-50.4 vs 51.4-51.5 us per
+// step; without receivers the 1024-workgroup chunks are faster)
+static IsoShape iso_stream_shape(const Geom &g, bool sampling) {
     IsoShape sh{2, iso_default_zchunk(g), 2, 4};
+    if (sampling) {
+        const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
+        sh.zc = adaptive_zchunk(cols, g.nz, 32, 2048, 2048);
+    }
     // grids with 2048 or more 64 x 16 tile chunks of 64 planes (512^3 and up)
     // take that shape (8 waves): half the y-halo rows and warm-up planes per
     // point of the 64 x 8 x 32 default (512^3: 451 vs 470 us per step)
@@ -200,7 +209,7 @@ static hipError_t launch_iso3d_image(const IsoArgs &a, hipStream_t s, const Laun
 // orders use the default shape.
 template <int R>
 static hipError_t launch_iso3d_stream(const IsoArgs &a, hipStream_t s, const LaunchEvents &ev) {
-    const IsoShape sh = iso_stream_shape(a.g);
+    const IsoShape sh = iso_stream_shape(a.g, a.sampling != 0);
     if (a.img_s) return launch_iso3d_image<R>(a, s, ev);
     // FDW_ISO_WIDE=1 takes the wide form on any grid (checks of that path)
     if (iso_wide_form(a.g, R))
@@ -297,10 +306,10 @@ hipError_t launch_iso_multi(int ndim, int R, const Geom &g, const void *recs, in
 #undef ISO_M
 }
 
-const char *iso_kernel_name(int ndim, int R, IsoVariant v, const Geom &g) {
+const char *iso_kernel_name(int ndim, int R, IsoVariant v, const Geom &g, bool sampling) {
     if (ndim == 3 && v == IsoVariant::Stream) {
         static thread_local char buf[96];
-        const IsoShape sh = iso_stream_shape(g);
+        const IsoShape sh = iso_stream_shape(g, sampling);
         if (iso_wide_form(g, R))
             std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x8 (4 waves) zchunk=%d prefetch=2 wide", sh.zc);
         else
