@@ -192,25 +192,32 @@ __device__ __forceinline__ float corner_damp(const SparseArgs &a, int p, int c) 
     return a.eta_x[b[0] + j0] + a.eta_z[b[2] + j1];
 }
 
-// Receiver sampling for one lane: group of ncorner lanes per receiver, lane
-// c owns corner c, the group's products are reduced with cross-lane shuffles
-// (groups of 4 or 8 lanes are aligned inside the 64-wide wavefront).
-__device__ __forceinline__ void interp_lane(const SparseArgs &a, int lane) {
-    const int p = lane / a.ncorner;
-    const int c = lane % a.ncorner;
+// Receiver sampling with linear weights (4 or 8 support points), one thread
+// per receiver p: the product of corner c, w[p][c] * u[base[p] + offset(c)]
+// (times 1 + a in the adjoint mode), summed as a fixed tree,
+// (c0 + c1) + (c2 + c3), plus (c4 + c5) + (c6 + c7) for 8 corners, so that
+// every kernel that samples a receiver gives the same bits.
+__device__ __forceinline__ void interp_receiver(const SparseArgs &a, int p) {
+#pragma clang fp contract(off)
     // global address space named: the arguments may come from a record in memory
     using gf = __attribute__((address_space(1))) const float;
     using gi = __attribute__((address_space(1))) const int64_t;
-    float v = 0.0f;
-    if (p < a.npoint) {
-        v = ((gf *)a.w)[(int64_t)p * a.ncorner + c] * ((gf *)a.field)[((gi *)a.base)[p] + corner_offset(a, c)];
-        if (a.damp_mode == 2) v *= 1.0f + corner_damp(a, p, c);
+    if (p >= a.npoint) return;
+    const int nc = a.ncorner;
+    const int64_t b = ((gi *)a.base)[p];
+    gf *w = (gf *)a.w + (int64_t)p * nc;
+    gf *u = (gf *)a.field;
+    float v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (c < nc) {
+            v[c] = w[c] * u[b + corner_offset(a, c)];
+            if (a.damp_mode == 2) v[c] *= 1.0f + corner_damp(a, p, c);
+        }
     }
-    // groups of 4 or 8 lanes are aligned inside the 64-wide wavefront
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    if (a.ncorner == 8) v += __shfl_xor(v, 4);
-    if (p < a.npoint && c == 0) ((__attribute__((address_space(1))) float *)a.rec_row)[p] = v;
+    float s = (v[0] + v[1]) + (v[2] + v[3]);
+    if (nc == 8) s += (v[4] + v[5]) + (v[6] + v[7]);
+    ((__attribute__((address_space(1))) float *)a.rec_row)[p] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -369,11 +376,9 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
     // workgroups past the stencil tiles sample the receivers of the previous
     // step from the current level, which this launch only reads
     if (bid >= nb_stencil) {
-        // a few workgroups loop over the receivers (groups of ncorner lanes
-        // stay together, so the shuffles always find their partners)
+        // a few workgroups loop over the receivers, one thread per receiver
         const int stride = ((int)gridDim.x - nb_stencil) * NT;
-        const int lanes = sp.npoint * sp.ncorner;
-        for (int l = (bid - nb_stencil) * NT + (int)threadIdx.x; l < lanes; l += stride) interp_lane(sp, l);
+        for (int p = (bid - nb_stencil) * NT + (int)threadIdx.x; p < sp.npoint; p += stride) interp_receiver(sp, p);
         return;
     }
     if (!stencil_live) return;
@@ -629,16 +634,16 @@ static inline int64_t interp_workgroups() {
     return n;
 }
 
-// Fused launch of n same-geometry shots (records in device memory); rec_lanes
-// = the largest npoint * ncorner of the shots' receiver rows.
+// Fused launch of n same-geometry shots (records in device memory); max_rec
+// = the most receivers of any shot's receiver row.
 template <int R, int NY, int PF, int BY, int NQ, int NP, class Op>
-static hipError_t launch_stream3d_multi(const StreamShot<Op, NQ, NP> *shots, int n, int64_t rec_lanes, const Geom &g,
+static hipError_t launch_stream3d_multi(const StreamShot<Op, NQ, NP> *shots, int n, int64_t max_rec, const Geom &g,
                                         int zc, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (zc > g.nz) zc = g.nz;
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + BY * NY - 1) / (BY * NY), ntz = (g.nz + zc - 1) / zc;
     const int64_t nb = (int64_t)ntx * nty * ntz;
-    const int64_t ni = std::min<int64_t>((rec_lanes + 64 * BY - 1) / (64 * BY), interp_workgroups());
+    const int64_t ni = std::min<int64_t>((max_rec + 64 * BY - 1) / (64 * BY), interp_workgroups());
     hipLaunchKernelGGL((stream3d_multi<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)(nb + ni), (unsigned)n),
                        dim3(64 * BY), 0, s, shots, g, zc, ntx, nty, 0, (int)nb);
     return hipGetLastError();
@@ -675,7 +680,7 @@ static hipError_t launch_stream3d(const Op &op, const StreamFields<NQ, NP> &F, c
     int64_t ni = 0;  // extra workgroups for receiver sampling
     if (sp && sp->npoint > 0) {
         spv = *sp;
-        ni = std::min<int64_t>(((int64_t)sp->npoint * sp->ncorner + 64 * BY - 1) / (64 * BY), interp_workgroups());
+        ni = std::min<int64_t>(((int64_t)sp->npoint + 64 * BY - 1) / (64 * BY), interp_workgroups());
     }
     // tile order: FDW_TILE_ORDER=z puts the z-chunk index fastest (tuning knob)
     const char *order = std::getenv("FDW_TILE_ORDER");

@@ -1267,7 +1267,7 @@ static int apply_impl(fdw_op *op, int time_m, int time_M, void *stream, float *s
     // the 3D streaming kernels sample the receivers of step t - 1 inside the
     // launch of step t (extra workgroups reading level t); the last step of the
     // apply is sampled by its own launch after the loop
-    const bool fuse_interp = nrec > 0 && op->ndim == 3 && !op->overlap_interp && interp_lanes_ok(itp) &&
+    const bool fuse_interp = nrec > 0 && op->ndim == 3 && !op->overlap_interp && interp_linear(itp) &&
                              (d.kind == FDW_ISO ? op->iso_v == IsoVariant::Stream : op->tti_v == TtiVariant::Stream);
     // saved level k occupies `fields` slots of the buffer (isotropic: u;
     // TTI: p then r)
@@ -1749,7 +1749,7 @@ int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, 
         return fdw_operator_apply(ops[0], time_m[0], time_M[0], stream);
     }
     int K = 0;
-    int64_t lanes = 0;
+    int64_t max_rec = 0;  // the most receivers of any shot
     for (int i = 0; i < n; ++i) {
         const fdw_op *op = ops[i];
         if (!op) return fail(FDW_ERR_ARG, "batch_apply: NULL op %d", i);
@@ -1775,13 +1775,13 @@ int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, 
         if ((nsrc > 0 && time_M[i] >= d.src->nt) || (nrec > 0 && time_M[i] >= d.rec->nt))
             return fail(FDW_ERR_ARG, "batch_apply: op %d: time_M = %d beyond the sparse time axis", i, time_M[i]);
         K = std::max(K, time_M[i] - time_m[i] + 1);
-        lanes = std::max(lanes, (int64_t)nrec * (1 << ndim));
+        max_rec = std::max<int64_t>(max_rec, nrec);
     }
     if (K == 0) return FDW_OK;
     hipStream_t s = (hipStream_t)stream;
     // 3D: receivers of step t are sampled in the launch of step t + 1, so one
     // more launch samples the last step; 2D: a sampling launch after each step
-    const int nl = (ndim == 3 && lanes > 0) ? K + 1 : K;
+    const int nl = (ndim == 3 && max_rec > 0) ? K + 1 : K;
     const size_t r1 = kind == FDW_ISO ? iso_multi_record_bytes(ndim) : tti_multi_record_bytes(ndim, 1);
     const size_t r2 = (kind == FDW_TTI && ndim == 3) ? tti_multi_record_bytes(3, 2) : 0;
     const size_t rs = ndim == 2 ? sizeof(SparseArgs) : 0;
@@ -1882,13 +1882,13 @@ int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, 
     auto launches = [&](hipStream_t st) -> hipError_t {
         for (int k = 0; k < nl; ++k) {
             const char *base = b->d_stage + (size_t)k * step_bytes;
-            const int64_t rl = ndim == 3 ? lanes : 0;
+            const int64_t rl = ndim == 3 ? max_rec : 0;
             hipError_t er = kind == FDW_ISO ? launch_iso_multi(ndim, R, o0->geom, base, n, rl, st)
                                             : launch_tti_multi(ndim, R, o0->geom, base, r2 ? base + off2 : nullptr, n,
                                                                rl, st);
             if (er != hipSuccess) return er;
-            if (ndim == 2 && lanes > 0) {
-                er = launch_interp_multi(reinterpret_cast<const SparseArgs *>(base + offs), n, lanes, st);
+            if (ndim == 2 && max_rec > 0) {
+                er = launch_interp_multi(reinterpret_cast<const SparseArgs *>(base + offs), n, max_rec, st);
                 if (er != hipSuccess) return er;
             }
         }
@@ -1902,7 +1902,7 @@ int fdw_batch_apply(fdw_batch *b, fdw_op *const *ops, int n, const int *time_m, 
         return FDW_OK;
     }
     const std::vector<int64_t> key = {kind, ndim, R, o0->geom.nx, o0->geom.ny, o0->geom.nz, o0->geom.sy, o0->geom.sz,
-                                      o0->geom.off0, n, nl, lanes, (int64_t)step_bytes, (int64_t)(intptr_t)b->d_stage,
+                                      o0->geom.off0, n, nl, max_rec, (int64_t)step_bytes, (int64_t)(intptr_t)b->d_stage,
                                       (int64_t)(intptr_t)s};
     if (!b->exec || key != b->key) {
         batch_drop_graph(b);

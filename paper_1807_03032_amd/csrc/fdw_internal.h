@@ -131,14 +131,15 @@ size_t iso_multi_record_bytes(int ndim);
 size_t tti_multi_record_bytes(int ndim, int stage);  // stage 1 or 2
 void multi_pack_iso(int ndim, const IsoArgs &a, bool live, const SparseArgs &rec, void *dst);
 void multi_pack_tti(int ndim, const TtiArgs &a, bool live, const SparseArgs &rec, void *dst1, void *dst2);
-hipError_t launch_iso_multi(int ndim, int R, const Geom &g, const void *recs, int n, int64_t rec_lanes,
+hipError_t launch_iso_multi(int ndim, int R, const Geom &g, const void *recs, int n, int64_t max_rec,
                             hipStream_t s);
 hipError_t launch_tti_multi(int ndim, int R, const Geom &g, const void *recs1, const void *recs2, int n,
-                            int64_t rec_lanes, hipStream_t s);
-hipError_t launch_interp_multi(const SparseArgs *recs, int n, int64_t max_lanes, hipStream_t s);
+                            int64_t max_rec, hipStream_t s);
+hipError_t launch_interp_multi(const SparseArgs *recs, int n, int64_t max_rec, hipStream_t s);
 
-// the lane-parallel receiver sampling reduces aligned groups of 4 or 8 lanes
-inline bool interp_lanes_ok(const SparseArgs &a) { return a.r == 2 && (a.ncorner == 4 || a.ncorner == 8); }
+// receivers with linear weights (4 or 8 support points): sampled by
+// interp_receiver, also inside the stencil launches
+inline bool interp_linear(const SparseArgs &a) { return a.r == 2 && (a.ncorner == 4 || a.ncorner == 8); }
 
 // Whole-run 2D isotropic kernel: one workgroup runs steps time_m..time_M of
 // a small 2D grid with the current level resident in LDS.

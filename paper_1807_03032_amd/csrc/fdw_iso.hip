@@ -287,10 +287,10 @@ void multi_pack_iso(int ndim, const IsoArgs &a, bool live, const SparseArgs &rec
 }
 
 template <int R>
-static hipError_t launch_iso_multi_r(int ndim, const Geom &g, const void *recs, int n, int64_t rec_lanes,
+static hipError_t launch_iso_multi_r(int ndim, const Geom &g, const void *recs, int n, int64_t max_rec,
                                      hipStream_t s) {
     if (ndim == 3) {
-        return launch_stream3d_multi<R, 2, 2, 4>(static_cast<const IsoShot3 *>(recs), n, rec_lanes, g,
+        return launch_stream3d_multi<R, 2, 2, 4>(static_cast<const IsoShot3 *>(recs), n, max_rec, g,
                                                  iso_default_zchunk(g), s);
     }
     dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.nz + 3) / 4, n);
@@ -298,10 +298,10 @@ static hipError_t launch_iso_multi_r(int ndim, const Geom &g, const void *recs, 
     return hipGetLastError();
 }
 
-hipError_t launch_iso_multi(int ndim, int R, const Geom &g, const void *recs, int n, int64_t rec_lanes,
+hipError_t launch_iso_multi(int ndim, int R, const Geom &g, const void *recs, int n, int64_t max_rec,
                             hipStream_t s) {
     if (n <= 0) return hipSuccess;
-#define ISO_M(r) launch_iso_multi_r<r>(ndim, g, recs, n, rec_lanes, s)
+#define ISO_M(r) launch_iso_multi_r<r>(ndim, g, recs, n, max_rec, s)
     FDW_DISPATCH_R(R, ISO_M)
 #undef ISO_M
 }

@@ -52,10 +52,8 @@ __global__ void __launch_bounds__(64 * BY) iso3d_tb2(TB3DFields a, Coefs cf, con
     if (bid >= nb_stencil) {  // receiver rows of the previous pass, one after the other
         const int stride = ((int)gridDim.x - nb_stencil) * NT;
         const int first = (bid - nb_stencil) * NT + (int)threadIdx.x;
-        const int lanes0 = rec0.npoint * rec0.ncorner;
-        for (int l = first; l < lanes0; l += stride) interp_lane(rec0, l);
-        const int lanes1 = rec1.npoint * rec1.ncorner;
-        for (int l = first; l < lanes1; l += stride) interp_lane(rec1, l);
+        for (int p = first; p < rec0.npoint; p += stride) interp_receiver(rec0, p);
+        for (int p = first; p < rec1.npoint; p += stride) interp_receiver(rec1, p);
         return;
     }
     constexpr int TX = 64 - 2 * R, TY1 = BY * NY, TY = TY1 - 2 * R;
@@ -282,9 +280,8 @@ static hipError_t launch_iso3d_tb2_r(const TB3DArgs &a, hipStream_t s, const Lau
     const int zc = tb3d_zchunk(g, R);
     const int ntx = (g.nx + sh.tx - 1) / sh.tx, nty = (g.ny + sh.ty - 1) / sh.ty, ntz = (g.nz + zc - 1) / zc;
     const int64_t nb = (int64_t)ntx * nty * ntz;
-    const int64_t lanes = std::max<int64_t>((int64_t)a.rec[0].npoint * a.rec[0].ncorner,
-                                            (int64_t)a.rec[1].npoint * a.rec[1].ncorner);
-    const int64_t ni = lanes > 0 ? std::min<int64_t>((lanes + 64 * BY - 1) / (64 * BY), interp_workgroups()) : 0;
+    const int64_t nrec = std::max<int64_t>(a.rec[0].npoint, a.rec[1].npoint);
+    const int64_t ni = nrec > 0 ? std::min<int64_t>((nrec + 64 * BY - 1) / (64 * BY), interp_workgroups()) : 0;
     hipExtLaunchKernelGGL((iso3d_tb2<R, NY, BY, PF>), dim3((unsigned)(nb + ni)), dim3(64 * BY), 0, s, ev.start,
                           ev.stop, 0, a.f, a.c, a.fsrc, a.q1, a.q2, a.rec[0], a.rec[1], zc, ntx, nty, (int)nb);
     return hipGetLastError();

@@ -1,19 +1,19 @@
-// Sparse-point kernels (gfx950): receiver interpolation (gather with
-// cross-lane reductions) and source injection (scatter with atomics), and the
-// halo-zeroing kernel.  Paper: arXiv 1807.03032, Section 3.2 (eq. interp,
+// Sparse-point kernels (gfx950): receiver interpolation (a gather, one thread
+// per receiver), source injection (scatter with atomics, or a gather per
+// target element), the standalone imaging kernels and the halo-zeroing kernel.  Paper: arXiv 1807.03032, Section 3.2 (eq. interp,
 // Listing finject).
 #include "fdw_device.h"
 
 namespace fdw {
 
 // ---------------------------------------------------------------------------
-// Sparse kernels.  One group of ncorner lanes per sparse point: lane c owns
-// corner c; interpolation reduces the group's products with cross-lane
-// shuffles; injection scatters with atomics (sources may share points).
+// Sparse kernels.  Interpolation: one thread per receiver (interp_receiver for
+// linear weights).  Injection by scatter: one lane per support point of a
+// source, atomics (sources may share points).
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) interp_kernel(SparseArgs a) {
-    interp_lane(a, blockIdx.x * blockDim.x + threadIdx.x);
+    interp_receiver(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Receiver sampling for supports other than 4 or 8 points: one thread per
@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(256) interp_point_kernel(SparseArgs a) {
 // Receiver rows of several shots in one launch: blockIdx.y selects the shot.
 __global__ void __launch_bounds__(256) interp_multi_kernel(const SparseArgs *__restrict__ recs) {
     const SparseArgs &a = recs[blockIdx.y];
-    interp_lane(a, blockIdx.x * blockDim.x + threadIdx.x);
+    interp_receiver(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) inject_kernel(SparseArgs a) {
@@ -157,18 +157,17 @@ hipError_t launch_inject(const SparseArgs &a, hipStream_t s) {
 
 hipError_t launch_interp(const SparseArgs &a, hipStream_t s) {
     if (a.npoint <= 0) return hipSuccess;
-    if (!interp_lanes_ok(a)) {
+    if (!interp_linear(a)) {
         hipLaunchKernelGGL(interp_point_kernel, dim3((unsigned)((a.npoint + 255) / 256)), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    const int64_t lanes = (int64_t)a.npoint * a.ncorner;
-    hipLaunchKernelGGL(interp_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(interp_kernel, dim3((unsigned)((a.npoint + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_interp_multi(const SparseArgs *recs, int n, int64_t max_lanes, hipStream_t s) {
-    if (n <= 0 || max_lanes <= 0) return hipSuccess;
-    hipLaunchKernelGGL(interp_multi_kernel, dim3((unsigned)((max_lanes + 255) / 256), (unsigned)n), dim3(256), 0, s,
+hipError_t launch_interp_multi(const SparseArgs *recs, int n, int64_t max_rec, hipStream_t s) {
+    if (n <= 0 || max_rec <= 0) return hipSuccess;
+    hipLaunchKernelGGL(interp_multi_kernel, dim3((unsigned)((max_rec + 255) / 256), (unsigned)n), dim3(256), 0, s,
                        recs);
     return hipGetLastError();
 }

@@ -86,8 +86,7 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
     constexpr int NT = 64 * BY;
     if (bid >= nb_stencil) {  // receiver sampling of the previous step (see stream3d_body)
         const int stride = ((int)gridDim.x - nb_stencil) * NT;
-        const int lanes = sp.npoint * sp.ncorner;
-        for (int l = (bid - nb_stencil) * NT + (int)threadIdx.x; l < lanes; l += stride) interp_lane(sp, l);
+        for (int p = (bid - nb_stencil) * NT + (int)threadIdx.x; p < sp.npoint; p += stride) interp_receiver(sp, p);
         return;
     }
     constexpr bool FLAT = flat_y<Op>::value;
@@ -286,7 +285,7 @@ static hipError_t launch_stream3d_ring(const Op &op, const StreamFields<NQ, NP> 
     int64_t ni = 0;
     if (sp && sp->npoint > 0) {
         spv = *sp;
-        ni = std::min<int64_t>(((int64_t)sp->npoint * sp->ncorner + 64 * BY - 1) / (64 * BY), interp_workgroups());
+        ni = std::min<int64_t>(((int64_t)sp->npoint + 64 * BY - 1) / (64 * BY), interp_workgroups());
     }
     hipExtLaunchKernelGGL((stream3d_ring<R, NY, PF, NQ, NP, BY, Op>), dim3((unsigned)(nb + ni)), dim3(64 * BY), 0, s,
                           e0, e1, 0, op, F, g, zc, ntx, nty, spv, (int)nb);

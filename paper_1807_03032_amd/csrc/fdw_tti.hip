@@ -366,12 +366,12 @@ void multi_pack_tti(int ndim, const TtiArgs &a, bool live, const SparseArgs &rec
 
 template <int R>
 static hipError_t launch_tti_multi_r(int ndim, const Geom &g, const void *recs1, const void *recs2, int n,
-                                     int64_t rec_lanes, hipStream_t s) {
+                                     int64_t max_rec, hipStream_t s) {
     if (ndim == 3) {
         constexpr int NY1 = 2, BY1 = 8, NY2 = 1, BY2 = 8;
         const int zc = tti_default_zchunk(g);
         hipError_t e = launch_stream3d_multi<R, NY1, tti_prefetch(R, 2, NY1, BY1), BY1>(
-            static_cast<const TtiShot1 *>(recs1), n, rec_lanes, g, zc, s);
+            static_cast<const TtiShot1 *>(recs1), n, max_rec, g, zc, s);
         if (e != hipSuccess) return e;
         return launch_stream3d_multi<R, NY2, 1, BY2>(static_cast<const TtiShot2 *>(recs2), n, 0, g, zc, s);
     }
@@ -385,9 +385,9 @@ static hipError_t launch_tti_multi_r(int ndim, const Geom &g, const void *recs1,
 }
 
 hipError_t launch_tti_multi(int ndim, int R, const Geom &g, const void *recs1, const void *recs2, int n,
-                            int64_t rec_lanes, hipStream_t s) {
+                            int64_t max_rec, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-#define TTI_M(r) launch_tti_multi_r<r>(ndim, g, recs1, recs2, n, rec_lanes, s)
+#define TTI_M(r) launch_tti_multi_r<r>(ndim, g, recs1, recs2, n, max_rec, s)
     FDW_DISPATCH_R(R, TTI_M)
 #undef TTI_M
 }
