@@ -76,6 +76,10 @@ class IsoModeling:
         self.a_out = torch.zeros((nt, nsrc), dtype=torch.float32, device=self.dev)
         self.a_src = fdw.fdw_sparse_bind(self.grid, "adj_src", self.rec_coords, nt, self.d_rev.data_ptr())
         self.a_rec = fdw.fdw_sparse_bind(self.grid, "adj_rec", self.src_coords, nt, self.a_out.data_ptr())
+        # torch loads a kernel's code on its first use in the process (about
+        # 50 ms for the time reversal): reverse a tiny tensor once here, so that
+        # adjoint() and gradient() spend their time on their own work
+        torch.flip(self.d_rev[:2], dims=[0])
 
         def desc(u_tf, src, rec, mode):
             d = fdw.fdw_op_desc()
