@@ -52,19 +52,38 @@ __global__ void __launch_bounds__(256) inject_kernel(SparseArgs a) {
 // divisor gathered per target at operator creation, so that few loads depend
 // on each other), summed in lane order and added once: no atomics, the same
 // bits on every run.  Taken for many sparse points.
+// A target's lanes are read four at a time (indices clamped to its last lane,
+// so every load is in bounds and none waits on a branch), which keeps the
+// loads of up to four lanes in flight together; the sum still runs in lane
+// order.
 __global__ void __launch_bounds__(256) inject_gather_kernel(SparseArgs a) {
+#pragma clang fp contract(off)
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.ntarget) return;
     const int64_t i = a.tgt[j];
+    const float f0 = a.field[i];  // this thread is the target's only writer
     const float rm = fast_rcp(a.m[i]);
     const float d = a.damp_mode == 1 ? a.gd[j] : 1.0f;
+    const int k0 = a.goff[j], k1 = a.goff[j + 1];
     float acc = 0.0f;
-    for (int k = a.goff[j]; k < a.goff[j + 1]; ++k) {
-        float v = a.gw[k] * a.q_row[a.gp[k]] * rm;
-        if (a.damp_mode == 1) v /= d;
-        acc += v;
+    for (int k = k0; k < k1; k += 4) {
+        float w[4], q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = min(k + u, k1 - 1);
+            w[u] = a.gw[kk];
+            q[u] = a.q_row[a.gp[kk]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (k + u < k1) {
+                float v = w[u] * q[u] * rm;
+                if (a.damp_mode == 1) v /= d;
+                acc += v;
+            }
+        }
     }
-    a.field[i] += acc;
+    a.field[i] = f0 + acc;
 }
 
 // Imaging condition of the adjoint-state gradient with respect to m, one
