@@ -620,3 +620,45 @@ def test_wide_fields_at_real_size(torch_dev, so, nt):
     np.testing.assert_array_equal(btr, str_)
     of, otr = oracle_run(small)
     check(small, {"u": tuple(blocks)}, btr, of, otr)
+
+
+_STRIDED_CHILD = """
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+from paper_1807_03032_amd import fdw
+from paper_1807_03032_amd import workloads as W
+fdw.load()
+kind, shape, so = sys.argv[3], tuple(int(s) for s in sys.argv[4].split("x")), int(sys.argv[5])
+prob = W.small_problem(kind, shape, so, nt=16, seed=77, nsrc=1, nrec=700)
+shot = fdw.Shot(prob, torch.device("cuda:0"), nslots=3)
+try:
+    shot.apply(0, prob.nt - 1)
+    np.save(sys.argv[2], shot.traces())
+finally:
+    shot.close()
+"""
+
+
+@pytest.mark.parametrize("kind,shape,so", [("iso", (70, 41, 33), 8), ("tti", (67, 35, 29), 12)])
+def test_receivers_beyond_one_per_sampling_thread(torch_dev, tmp_path, kind, shape, so):
+    """700 receivers sampled inside the stencil launches by one sampling
+    workgroup (FDW_INTERP_WG=1, set for a child process: the library reads it
+    once), so that each sampling thread takes several receivers in turn: the
+    traces equal those of the default launch (several sampling workgroups)
+    bit for bit, and the oracle's."""
+    import subprocess
+    prob = W.small_problem(kind, shape, so, nt=16, seed=77, nsrc=1, nrec=700)
+    say("strided receiver sampling", kind, shape, so)
+    f, tr, desc = gpu_run(prob, torch_dev)
+    assert "nrec=700" in desc and "stream" in desc, desc
+    out = str(tmp_path / "traces.npy")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, FDW_INTERP_WG="1")
+    r = subprocess.run([sys.executable, "-c", _STRIDED_CHILD, root, out, kind, "x".join(map(str, shape)), str(so)],
+                       env=env, timeout=240, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    np.testing.assert_array_equal(np.load(out), tr)
+    of, otr = oracle_run(prob)
+    check(prob, f, tr, of, otr)
