@@ -1,6 +1,6 @@
 // Bandwidth probes (gfx950): plain streaming kernels of known traffic that
 // measure the HBM bandwidth the chip attains, the reference against which the
-// stencil kernels' achieved bandwidth is judged (the paper's Section 7.1 takes
+// stencil kernels' achieved bandwidth is compared (the paper's Section 7.1 takes
 // the STREAM triad rate as the attainable peak of its roofline plots).
 #include "fdw_internal.h"
 
