@@ -57,8 +57,9 @@ def parse():
                     help="also time one gradient (forward with checkpoints + recomputation + adjoint + imaging) "
                          "on the 320^3 so=8 1500-step workload")
     ap.add_argument("--serve", action="store_true",
-                    help="also run the served shot stream (Poisson arrivals, mixed sizes, kinds and orders): "
-                         "p50/p99 latency and aggregate GPts/s against sequential per-shot solves")
+                    help="no effect: the served shot stream (Poisson arrivals, mixed sizes, kinds and orders; "
+                         "p50/p99 latency and aggregate GPts/s against sequential per-shot solves) runs by "
+                         "default, --no-serve skips it")
     ap.add_argument("--serve-count", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=3.0, help="mean request arrivals per second")
     ap.add_argument("--serve-streams", type=int, default=4, help="server streams (buckets advance concurrently)")
