@@ -234,13 +234,17 @@ struct TtiShape {
 };
 
 // z-chunk of both stages: 64 for large grids, shorter when stage 2's 64 x 8
-// tile columns are too few to occupy the chip; then evened out over the
-// chunks the walk needs (400 planes: 7 chunks of 58 instead of six of 64 and
-// one of 16, whose workgroups ran alone at the end: 1348 -> 1289 us per step
-// at space order 12)
+// tile columns are too few to occupy the chip, down to the longest chunk
+// that still gives 1792 workgroups (three and a half rounds of the 512
+// eight-wavefront slots; shorter chunks re-read 2R warm-up planes each:
+// 300^3 order 12, 32 planes, 588 vs 615 us per step with 16; 200^3 keeps 8
+// planes, 222 vs 229 us with 16); then evened out over the chunks the walk
+// needs (400 planes: 7 chunks of 58 instead of six of 64 and one of 16,
+// whose workgroups ran alone at the end: 1348 -> 1289 us per step at space
+// order 12)
 static int tti_default_zchunk(const Geom &g) {
     const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
-    const int zc = adaptive_zchunk(cols, g.nz, 64, 2048, 2048);
+    const int zc = adaptive_zchunk(cols, g.nz, 64, 2048, 1792);
     const int n = (g.nz + zc - 1) / zc;
     return (g.nz + n - 1) / n;
 }
