@@ -77,8 +77,8 @@ static int iso_default_zchunk(const Geom &g) {
 // sampling: receivers are sampled by extra workgroups of the launch, which
 // the hardware dispatches after the stencil workgroups; chunks that give two
 // rounds of stencil workgroups (2048 rather than 1024) let them overlap the
-// second round (256^3 with 65,536 receivers: 50.2-50.4 vs 51.4-51.5 us per
-// step; without receivers the 1024-workgroup chunks are faster)
+// second round (256^3 with 65,536 receivers: 49.0-50.0 vs 50.7 us per step;
+// without receivers the 1024-workgroup chunks are faster)
 static IsoShape iso_stream_shape(const Geom &g, bool sampling) {
     IsoShape sh{2, iso_default_zchunk(g), 2, 4};
     if (sampling) {
