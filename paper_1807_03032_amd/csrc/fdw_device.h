@@ -283,6 +283,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc2(const float *base) {
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vb, int soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, soff, 0));
 }
+// The same load with the non-temporal hint: for fields read once per step,
+// so that the cache keeps the lines that are read again (halo rows, warm-up
+// planes of the stencil field) instead.
+__device__ __forceinline__ float bload_nt(__amdgpu_buffer_rsrc_t r, uint32_t vb, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, soff, 2));
+}
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vb, int soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)vb, soff, 0);
 }

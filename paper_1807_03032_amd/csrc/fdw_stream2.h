@@ -45,6 +45,14 @@ struct flat_y : std::false_type {};
 template <class Op>
 struct flat_y<Op, std::void_t<decltype(Op::kFlatY)>> : std::integral_constant<bool, Op::kFlatY> {};
 
+// Operators on grids beyond the last-level cache declare kStreamingPointwise:
+// the engine then reads their pointwise fields with the non-temporal hint.
+template <class Op, class = void>
+struct streaming_pw : std::false_type {};
+template <class Op>
+struct streaming_pw<Op, std::void_t<decltype(Op::kStreamingPointwise)>>
+    : std::integral_constant<bool, Op::kStreamingPointwise> {};
+
 // Ring length: 2R + 1 + PF rounded up to a multiple of PF + 1 (pointwise
 // rings) and of 2 (LDS double buffer).
 constexpr int ring_len(int R, int PF) {
@@ -90,6 +98,7 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
         return;
     }
     constexpr bool FLAT = flat_y<Op>::value;
+    constexpr bool SPW = streaming_pw<Op>::value;
     constexpr int RY = FLAT ? 0 : R;  // y-halo rows above the tile in LDS
     constexpr int TX = 64, TY = BY * NY, LW = (TX + 2 * R + 63) / 64 * 64, LH = TY + 2 * RY;
     constexpr int RING = ring_len(R, PF), PR = PF + 1;
@@ -188,7 +197,7 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
 #pragma unroll
             for (int f = 0; f < NP; ++f)
 #pragma unroll
-                for (int c = 0; c < NY; ++c) pw[f][c][P] = bload(rp[f], vcol[c], so);
+                for (int c = 0; c < NY; ++c) pw[f][c][P] = SPW ? bload_nt(rp[f], vcol[c], so) : bload(rp[f], vcol[c], so);
 #pragma unroll
             for (int f = 0; f < NQ; ++f) {
 #pragma unroll
