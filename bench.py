@@ -460,15 +460,16 @@ def summarize_traffic(fetch_csv, write_csv):
 def iso_kernel_match(desc):
     """Kernel-name fragments of the isotropic operator described by desc: the
     streaming kernel's template arguments <R, NY, PF, NQ, NP, BY> follow from
-    its tile, wavefront count and prefetch distance (one-thread-per-point
-    kernels otherwise)."""
+    its tile, wavefront count and prefetch distance, its operator type from
+    the pointwise loads' hint (one-thread-per-point kernels otherwise)."""
     import re
 
     m = re.search(r"tile=64x(\d+) \((\d+) waves\).*prefetch=(\d+).* R=(\d+)", desc)
     if not m:
         return ["iso_naive"]
     ty, by, pf, r = (int(v) for v in m.groups())
-    return [f"<{r}, {ty // by}, {pf}, 1, 2, {by}, fdw::IsoOp>"]
+    op = "IsoOpNT" if "pointwise=nt" in desc else "IsoOp"
+    return [f"<{r}, {ty // by}, {pf}, 1, 2, {by}, fdw::{op}>"]
 
 
 def load_traffic(kind, desc):
