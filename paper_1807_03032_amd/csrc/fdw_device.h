@@ -328,10 +328,20 @@ using gfloat = __attribute__((address_space(1))) float;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_at(const float *base, bool valid) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, valid ? (int)kBufOut : 0, 0x00020000);
 }
-template <bool BUF>
+// Operators on grids beyond the last-level cache declare kStreamingPointwise:
+// both engines then read their pointwise fields with the non-temporal hint
+// (raw buffer accesses only).
+template <class Op, class = void>
+struct streaming_pw : std::false_type {};
+template <class Op>
+struct streaming_pw<Op, std::void_t<decltype(Op::kStreamingPointwise)>>
+    : std::integral_constant<bool, Op::kStreamingPointwise> {};
+
+template <bool BUF, bool NT = false>
 __device__ __forceinline__ float load_at(const float *f, int64_t zo, uint32_t vb, bool valid = true) {
     if constexpr (BUF)
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(buffer_at(f + zo, valid), (int)vb, 0, 0));
+        return __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(buffer_at(f + zo, valid), (int)vb, 0, NT ? 2 : 0));
     else
         return valid && vb != kBufOut ? *(const gfloat *)((const char *)f + ((uint32_t)zo * 4u + vb)) : 0.0f;
 }
@@ -424,7 +434,7 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
         return load_at<BUF>(F.q[f], pbase + (int64_t)z * g.sz, vb, valid);
     };
     auto ldp = [&](int f, int z, uint32_t vb) -> float {
-        return load_at<BUF>(F.p[f], pbase + (int64_t)z * g.sz, vb, true);
+        return load_at<BUF, streaming_pw<Op>::value>(F.p[f], pbase + (int64_t)z * g.sz, vb, true);
     };
     auto vbyte = [&](int xx, int yy) {
         return xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny ? (uint32_t)(((int64_t)yy * g.sy + xx) * 4) : kBufOut;

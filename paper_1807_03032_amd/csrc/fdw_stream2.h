@@ -45,14 +45,6 @@ struct flat_y : std::false_type {};
 template <class Op>
 struct flat_y<Op, std::void_t<decltype(Op::kFlatY)>> : std::integral_constant<bool, Op::kFlatY> {};
 
-// Operators on grids beyond the last-level cache declare kStreamingPointwise:
-// the engine then reads their pointwise fields with the non-temporal hint.
-template <class Op, class = void>
-struct streaming_pw : std::false_type {};
-template <class Op>
-struct streaming_pw<Op, std::void_t<decltype(Op::kStreamingPointwise)>>
-    : std::integral_constant<bool, Op::kStreamingPointwise> {};
-
 // Ring length: 2R + 1 + PF rounded up to a multiple of PF + 1 (pointwise
 // rings) and of 2 (LDS double buffer).
 constexpr int ring_len(int R, int PF) {

@@ -321,18 +321,40 @@ static void tti_stage2_parts(const TtiArgs &a, TtiS2Op &o2, StreamFields<3, 8> &
     for (int i = 0; i < 8; ++i) F2.p[i] = pw[i];
 }
 
-template <int R>
-static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {
+// Grids whose step working set exceeds the 256 MB last-level cache read the
+// stages' once-read pointwise fields with the non-temporal hint, leaving L2
+// to the stencil fields' re-read halo rows and warm-up planes.  FDW_TTI_NT=0/1
+// overrides the choice.
+static bool tti_streaming_hint(const Geom &g, int R) {
+    if (const char *e = std::getenv("FDW_TTI_NT")) return e[0] == '1';
+    const double field = (double)g.sz * (double)(g.nz + 2 * R) * 4.0;
+    return 11.0 * field > 256.0 * 1024.0 * 1024.0;
+}
+struct TtiS1OpNT : TtiS1Op {
+    static constexpr bool kStreamingPointwise = true;
+};
+struct TtiS2OpNT : TtiS2Op {
+    static constexpr bool kStreamingPointwise = true;
+};
+
+template <int R, class Op1, class Op2>
+static hipError_t launch_tti3d_stream_ops(const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {
     const TtiShape sh = tti_stream_shape(a.g, R);
-    TtiS1Op o1;
+    Op1 o1;
     StreamFields<2, 2> F1;
-    tti_stage1_parts(a, o1, F1);
+    tti_stage1_parts(a, static_cast<TtiS1Op &>(o1), F1);
     hipError_t e = launch_tti_stage_shape<R>(sh.ny1, sh.by1, o1, F1, a.g, sh.zc, s, ev.start, nullptr, a.rec);
     if (e != hipSuccess) return e;
-    TtiS2Op o2;
+    Op2 o2;
     StreamFields<3, 8> F2;
-    tti_stage2_parts(a, o2, F2);
+    tti_stage2_parts(a, static_cast<TtiS2Op &>(o2), F2);
     return launch_tti_stage_shape<R>(sh.ny2, sh.by2, o2, F2, a.g, sh.zc, s, nullptr, ev.stop);
+}
+
+template <int R>
+static hipError_t launch_tti3d_stream(const TtiArgs &a, hipStream_t s, const LaunchEvents &ev) {
+    if (tti_streaming_hint(a.g, R)) return launch_tti3d_stream_ops<R, TtiS1OpNT, TtiS2OpNT>(a, s, ev);
+    return launch_tti3d_stream_ops<R, TtiS1Op, TtiS2Op>(a, s, ev);
 }
 
 // ---------------------------------------------------------------------------
@@ -421,8 +443,8 @@ const char *tti_kernel_name(int ndim, int R, TtiVariant v, const Geom &g) {
     if (ndim == 3 && v == TtiVariant::Stream) {
         static thread_local char buf[96];
         const TtiShape sh = tti_stream_shape(g, R);
-        std::snprintf(buf, sizeof(buf), "tti3d_stream stage1 tile=64x%d stage2 tile=64x%d zchunk=%d", sh.by1 * sh.ny1,
-                      sh.by2 * sh.ny2, sh.zc);
+        std::snprintf(buf, sizeof(buf), "tti3d_stream stage1 tile=64x%d stage2 tile=64x%d zchunk=%d%s",
+                      sh.by1 * sh.ny1, sh.by2 * sh.ny2, sh.zc, tti_streaming_hint(g, R) ? " pointwise=nt" : "");
         return buf;
     }
     return ndim == 3 ? "tti_naive_stage1+2<3>" : "tti_naive_stage1+2<2>";

@@ -662,3 +662,21 @@ def test_receivers_beyond_one_per_sampling_thread(torch_dev, tmp_path, kind, sha
     np.testing.assert_array_equal(np.load(out), tr)
     of, otr = oracle_run(prob)
     check(prob, f, tr, of, otr)
+
+
+def test_tti_nontemporal_pointwise_loads_change_no_bit(torch_dev, monkeypatch):
+    """Grids beyond the last-level cache read the TTI stages' pointwise fields
+    with the non-temporal hint; forced on and off here (FDW_TTI_NT) on a
+    multi-tile grid, the hint changes no bit of the levels or the traces."""
+    prob = W.small_problem("tti", (150, 70, 90), 12, nt=12, seed=321, nsrc=2, nrec=40, nbl=6)
+    say("tti non-temporal hint", prob.shape)
+    runs = {}
+    for nt in ("1", "0"):
+        monkeypatch.setenv("FDW_TTI_NT", nt)
+        f, tr, desc = gpu_run(prob, torch_dev)
+        assert ("pointwise=nt" in desc) == (nt == "1"), desc
+        runs[nt] = (f, tr)
+    for nm in runs["1"][0]:
+        for k in (0, 1):
+            np.testing.assert_array_equal(runs["1"][0][nm][k], runs["0"][0][nm][k])
+    np.testing.assert_array_equal(runs["1"][1], runs["0"][1])
