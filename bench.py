@@ -468,7 +468,7 @@ def iso_kernel_match(desc):
     if not m:
         return ["iso_naive"]
     ty, by, pf, r = (int(v) for v in m.groups())
-    op = "IsoOpNT" if "pointwise=nt" in desc else "IsoOp"
+    op = "IsoOpNTu" if "pointwise=nt(u" in desc else "IsoOpNT" if "pointwise=nt" in desc else "IsoOp"
     return [f"<{r}, {ty // by}, {pf}, 1, 2, {by}, fdw::{op}>"]
 
 

@@ -336,6 +336,12 @@ struct streaming_pw : std::false_type {};
 template <class Op>
 struct streaming_pw<Op, std::void_t<decltype(Op::kStreamingPointwise)>>
     : std::integral_constant<bool, Op::kStreamingPointwise> {};
+// the pointwise fields that take the hint (bit f: field f), all by default
+template <class Op, class = void>
+struct streaming_mask : std::integral_constant<unsigned, ~0u> {};
+template <class Op>
+struct streaming_mask<Op, std::void_t<decltype(Op::kStreamingMask)>>
+    : std::integral_constant<unsigned, Op::kStreamingMask> {};
 
 template <bool BUF, bool NT = false>
 __device__ __forceinline__ float load_at(const float *f, int64_t zo, uint32_t vb, bool valid = true) {

@@ -136,20 +136,27 @@ static bool iso_wide_form(const Geom &g, int R) {
 }
 static StreamFields<1, 2> iso_fields(const IsoArgs &a);
 
-// Grids whose step working set (two levels and m) exceeds the 256 MB
-// last-level cache read their pointwise fields (u(t-1), m; the imaging step's
-// S and gradient too) with the non-temporal hint: the L2 then keeps more of
-// the stencil field's re-read halo rows and warm-up planes (512^3: counted
-// traffic 1.18 -> 1.09x, 449.7 -> 438.5 us per step).  Smaller grids keep
-// these fields in the last-level cache from step to step, which the hint
-// gives up (256^3: 49.5 -> 53.5 us).  FDW_ISO_NT=0/1 overrides the choice.
-static bool iso_streaming_hint(const Geom &g, int R) {
-    if (const char *e = std::getenv("FDW_ISO_NT")) return e[0] == '1';
+// Pointwise fields read with the non-temporal hint, so that the L2 keeps more
+// of the stencil field's re-read halo rows and warm-up planes:
+//   2: all of them (u(t-1), m; the imaging step's S and gradient too) on
+//      grids whose step working set (two levels and m) exceeds the 256 MB
+//      last-level cache (512^3: counted traffic 1.18 -> 1.09x, 449.7 ->
+//      438.5 us per step);
+//   1: u(t-1) only on smaller grids, which keep m in the last-level cache
+//      from step to step (256^3: 48.8 -> 48.3 us; with m too, 53.5 us);
+//   0: none.
+// FDW_ISO_NT=0/u/1 overrides the choice (0, 1, 2).
+static int iso_streaming_mode(const Geom &g, int R) {
+    if (const char *e = std::getenv("FDW_ISO_NT")) return e[0] == '1' ? 2 : e[0] == 'u' ? 1 : 0;
     const double field = (double)g.sz * (double)(g.nz + 2 * R) * 4.0;
-    return 3.0 * field > 256.0 * 1024.0 * 1024.0;
+    return 3.0 * field > 256.0 * 1024.0 * 1024.0 ? 2 : 1;
 }
 struct IsoOpNT : IsoOp {
     static constexpr bool kStreamingPointwise = true;
+};
+struct IsoOpNTu : IsoOp {  // u(t-1) only
+    static constexpr bool kStreamingPointwise = true;
+    static constexpr unsigned kStreamingMask = 1u;
 };
 struct IsoImgOpNT : IsoImgOp {
     static constexpr bool kStreamingPointwise = true;
@@ -159,8 +166,12 @@ template <int R, int NY, int PF, int BY>
 static hipError_t launch_iso3d_stream_cfg(const IsoArgs &a, int zc, hipStream_t s, const LaunchEvents &ev) {
     if constexpr (R <= 4) {
         if (iso_ring_engine(R)) {
-            if (iso_streaming_hint(a.g, R))
+            const int mode = iso_streaming_mode(a.g, R);
+            if (mode == 2)
                 return launch_stream3d_ring<R, NY, PF, BY>(IsoOpNT{make_iso_op(a)}, iso_fields(a), a.g, zc, s,
+                                                           ev.start, ev.stop, a.rec);
+            if (mode == 1)
+                return launch_stream3d_ring<R, NY, PF, BY>(IsoOpNTu{make_iso_op(a)}, iso_fields(a), a.g, zc, s,
                                                            ev.start, ev.stop, a.rec);
             return launch_stream3d_ring<R, NY, PF, BY>(make_iso_op(a), iso_fields(a), a.g, zc, s, ev.start, ev.stop,
                                                        a.rec);
@@ -218,7 +229,7 @@ static hipError_t launch_iso3d_image(const IsoArgs &a, hipStream_t s, const Laun
     const int zc = image_zchunk(a.g);
     if constexpr (R <= 4) {
         if (iso_ring_engine(R)) {
-            if (iso_streaming_hint(a.g, R)) {
+            if (iso_streaming_mode(a.g, R) == 2) {
                 IsoImgOpNT w;
                 static_cast<IsoImgOp &>(w) = op;
                 return launch_stream3d_ring<R, 2, 1, 4>(w, F, a.g, zc, s, ev.start, ev.stop, a.rec);
@@ -344,7 +355,10 @@ const char *iso_kernel_name(int ndim, int R, IsoVariant v, const Geom &g, bool s
         else
             std::snprintf(buf, sizeof(buf), "iso3d_stream tile=64x%d (%d waves) zchunk=%d prefetch=%d%s",
                           sh.by * sh.ny, sh.by, sh.zc, sh.pf,
-                          iso_ring_engine(R) && iso_streaming_hint(g, R) ? " pointwise=nt" : "");
+                          !iso_ring_engine(R)                 ? ""
+                          : iso_streaming_mode(g, R) == 2 ? " pointwise=nt"
+                          : iso_streaming_mode(g, R) == 1 ? " pointwise=nt(u(t-1))"
+                                                          : "");
         return buf;
     }
     if (ndim == 2 && v == IsoVariant::Stream && R < 8) {

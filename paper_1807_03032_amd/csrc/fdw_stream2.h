@@ -189,7 +189,9 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
 #pragma unroll
             for (int f = 0; f < NP; ++f)
 #pragma unroll
-                for (int c = 0; c < NY; ++c) pw[f][c][P] = SPW ? bload_nt(rp[f], vcol[c], so) : bload(rp[f], vcol[c], so);
+                for (int c = 0; c < NY; ++c)
+                    pw[f][c][P] = SPW && ((streaming_mask<Op>::value >> f) & 1u) ? bload_nt(rp[f], vcol[c], so)
+                                                                                : bload(rp[f], vcol[c], so);
 #pragma unroll
             for (int f = 0; f < NQ; ++f) {
 #pragma unroll

@@ -242,25 +242,28 @@ def test_adjoint_320_full_size_properties(dev):
 
 
 def test_nontemporal_pointwise_loads_change_no_bit(dev, monkeypatch):
-    """Grids beyond the last-level cache read the pointwise fields of the
-    forward and imaging steps with the non-temporal hint; forced on and off
-    here (FDW_ISO_NT) on a small grid, the hint changes no bit of the
-    gradient, the receiver traces or the forward levels."""
+    """The pointwise fields of the forward and imaging steps are read with the
+    non-temporal hint (all of them beyond the last-level cache, u(t-1) only
+    below); forced to each mode here (FDW_ISO_NT) on a small grid, the hint
+    changes no bit of the gradient, the receiver traces or the forward
+    levels."""
     from paper_1807_03032_amd import fdw
     prob = problem(3, 8, 24, 160)
     rng = np.random.default_rng(10)
     d = rng.standard_normal((prob.nt, prob.rec_coords.shape[0]))
     out = {}
-    for nt in ("1", "0"):
+    expect = {"1": " pointwise=nt ", "u": " pointwise=nt(u(t-1)) ", "0": None}
+    for nt in ("1", "u", "0"):
         monkeypatch.setenv("FDW_ISO_NT", nt)
         md = model_for(prob, dev, None)
         try:
             desc = fdw.fdw_operator_describe(md.fwd)[0]
-            assert ("pointwise=nt" in desc) == (nt == "1"), desc
+            assert (expect[nt] in desc) if expect[nt] else ("pointwise" not in desc), desc
             rec = md.forward(prob.src).cpu().numpy()
             out[nt] = (rec, md.u.cpu().numpy(), md.gradient(d).cpu().numpy())
         finally:
             md.close()
     say("non-temporal hint", [float(np.abs(x).max()) for x in out["1"]])
-    for a, b in zip(out["1"], out["0"]):
-        np.testing.assert_array_equal(a, b)
+    for nt in ("1", "u"):
+        for a, b in zip(out[nt], out["0"]):
+            np.testing.assert_array_equal(a, b)
