@@ -50,6 +50,17 @@ struct IsoOp2D {
     }
 };
 
+// Grids whose step working set (two levels and m) exceeds the 256 MB
+// last-level cache read u(t-1) and m with the non-temporal hint, leaving L2 to
+// the re-read halo columns and warm-up rows of u (FDW_ISO2D_NT=0/1 overrides).
+struct IsoOp2DNT : IsoOp2D {
+    static constexpr bool kStreamingPointwise = true;
+};
+static bool iso2d_streaming_hint(const Geom &g) {
+    if (const char *e = std::getenv("FDW_ISO2D_NT")) return e[0] == '1';
+    return 3.0 * (double)g.sz * (double)g.nz * 4.0 > 256.0 * 1024.0 * 1024.0;
+}
+
 // z-chunk: the longest of 64, 32, ... planes that still gives 2048
 // workgroups (one 64-column wavefront each), at least 4 (FDW_ISO2D_ZC
 // overrides the longest, for tuning: at 8001^2 so 8, 64 planes 230 us per
@@ -79,6 +90,11 @@ static hipError_t launch_stream2d_r(const IsoArgs &a, hipStream_t s, const Launc
     F.q[0] = a.u_cur;
     F.p[0] = a.u_prev;
     F.p[1] = a.m;
+    if (iso2d_streaming_hint(a.g)) {
+        IsoOp2DNT w;
+        static_cast<IsoOp2D &>(w) = op;
+        return launch_stream3d_ring<R, 1, 2, 1>(w, F, a.g, iso2d_zchunk(a.g), s, ev.start, ev.stop, nullptr);
+    }
     return launch_stream3d_ring<R, 1, 2, 1>(op, F, a.g, iso2d_zchunk(a.g), s, ev.start, ev.stop, nullptr);
 }
 

@@ -680,3 +680,20 @@ def test_tti_nontemporal_pointwise_loads_change_no_bit(torch_dev, monkeypatch):
         for k in (0, 1):
             np.testing.assert_array_equal(runs["1"][0][nm][k], runs["0"][0][nm][k])
     np.testing.assert_array_equal(runs["1"][1], runs["0"][1])
+
+
+def test_iso2d_nontemporal_pointwise_loads_change_no_bit(torch_dev, monkeypatch):
+    """Large 2D grids read u(t-1) and m with the non-temporal hint; forced on
+    and off here (FDW_ISO2D_NT) on a grid too large for the LDS-resident
+    kernel, the hint changes no bit of the levels or the traces."""
+    prob = W.small_problem("iso", (600, 500), 8, nt=30, seed=322, nsrc=2, nrec=40)
+    say("iso2d non-temporal hint", prob.shape)
+    runs = {}
+    for nt in ("1", "0"):
+        monkeypatch.setenv("FDW_ISO2D_NT", nt)
+        f, tr, desc = gpu_run(prob, torch_dev)
+        assert "iso2d_stream" in desc, desc
+        runs[nt] = (f, tr)
+    for k in (0, 1):
+        np.testing.assert_array_equal(runs["1"][0]["u"][k], runs["0"][0]["u"][k])
+    np.testing.assert_array_equal(runs["1"][1], runs["0"][1])
