@@ -328,9 +328,10 @@ using gfloat = __attribute__((address_space(1))) float;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_at(const float *base, bool valid) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, valid ? (int)kBufOut : 0, 0x00020000);
 }
-// Operators on grids beyond the last-level cache declare kStreamingPointwise:
-// both engines then read their pointwise fields with the non-temporal hint
-// (raw buffer accesses only).
+// Operators declare kStreamingPointwise to have their pointwise fields read
+// with the non-temporal hint (raw buffer accesses only; the launchers pick
+// such operator types by grid size).  kStreamingMask narrows the ring
+// engine's hint to some of the fields; the shifting-queue engine hints all.
 template <class Op, class = void>
 struct streaming_pw : std::false_type {};
 template <class Op>

@@ -18,7 +18,9 @@
 //     whole ring, so every ring index is a compile-time constant: no register
 //     shifts between planes;
 //   * pointwise fields and the in-plane halo are prefetched PF planes ahead
-//     into rings of PF + 1 entries (the ring length is a multiple of PF + 1).
+//     into rings of PF + 1 entries (the ring length is a multiple of PF + 1);
+//     pointwise fields can be read with the non-temporal hint (streaming_pw),
+//     so that the cache keeps the stencil field's re-read rows and planes.
 // Fields of any size whose planes fit the chunk span (buffer_planes_fit).
 #pragma once
 #include "fdw_device.h"
