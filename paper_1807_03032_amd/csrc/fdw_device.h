@@ -352,11 +352,18 @@ __device__ __forceinline__ float load_at(const float *f, int64_t zo, uint32_t vb
     else
         return valid && vb != kBufOut ? *(const gfloat *)((const char *)f + ((uint32_t)zo * 4u + vb)) : 0.0f;
 }
-template <bool BUF>
+// the stores of operators that declare kStreamingStores take the hint too
+template <class Op, class = void>
+struct streaming_st : std::false_type {};
+template <class Op>
+struct streaming_st<Op, std::void_t<decltype(Op::kStreamingStores)>>
+    : std::integral_constant<bool, Op::kStreamingStores> {};
+
+template <bool BUF, bool NT = false>
 __device__ __forceinline__ void store_at(float *f, int64_t zo, uint32_t vb, float v) {
     if constexpr (BUF)
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), buffer_at(f + zo, true), (int)vb, 0,
-                                              0);
+                                              NT ? 2 : 0);
     else if (vb != kBufOut)
         *(gfloat *)((char *)f + ((uint32_t)zo * 4u + vb)) = v;
 }
@@ -372,7 +379,7 @@ struct PlaneLoads {
 };
 
 // What an operator sees for one output point.
-template <int R, int NQ, int NP, int NY, int LH, int LW, int DIR, bool BUF>
+template <int R, int NQ, int NP, int NY, int LH, int LW, int DIR, bool BUF, bool NTS = false>
 struct StreamPoint {
     const float (&q)[NQ][NY][2 * R + 1];
     const float (&lds)[NQ][LH][LW];
@@ -388,7 +395,7 @@ struct StreamPoint {
     __device__ __forceinline__ float qy(int f, int k) const { return lds[f][ly + k][lx]; }
     __device__ __forceinline__ float p(int i) const { return pw[i][j]; }
     // stores v at the point's element of an output field in the same layout
-    __device__ __forceinline__ void store(float *f, float v) const { store_at<BUF>(f, zb, vb, v); }
+    __device__ __forceinline__ void store(float *f, float v) const { store_at<BUF, NTS>(f, zb, vb, v); }
 };
 
 template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
@@ -572,7 +579,7 @@ __device__ __forceinline__ void stream3d_body(const Op &op, const StreamFields<N
                 lds_barrier();
 #pragma unroll
                 for (int j = 0; j < NY; ++j) {
-                    StreamPoint<R, NQ, NP, NY, LH, LW, DIR, BUF> pt{q,
+                    StreamPoint<R, NQ, NP, NY, LH, LW, DIR, BUF, streaming_st<Op>::value> pt{q,
                                                                     lds[buf],
                                                                     cpw,
                                                                     j,
