@@ -292,6 +292,10 @@ __device__ __forceinline__ float bload_nt(__amdgpu_buffer_rsrc_t r, uint32_t vb,
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vb, int soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)vb, soff, 0);
 }
+// the same store with the non-temporal hint
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, uint32_t vb, int soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)vb, soff, 2);
+}
 
 // Planes one chunk descriptor spans beyond the chunk itself.
 constexpr int buffer_extra_planes(int R, int PF) { return 2 * (R + PF); }

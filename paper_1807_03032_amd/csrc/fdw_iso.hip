@@ -151,8 +151,9 @@ static int iso_streaming_mode(const Geom &g, int R) {
     const double field = (double)g.sz * (double)(g.nz + 2 * R) * 4.0;
     return 3.0 * field > 256.0 * 1024.0 * 1024.0 ? 2 : 1;
 }
-struct IsoOpNT : IsoOp {
+struct IsoOpNT : IsoOp {  // u(t + 1) written with the hint too (512^3: 439.4 -> 431 us)
     static constexpr bool kStreamingPointwise = true;
+    static constexpr bool kStreamingStores = true;
 };
 struct IsoOpNTu : IsoOp {  // u(t-1) only
     static constexpr bool kStreamingPointwise = true;

@@ -56,7 +56,7 @@ constexpr int ring_len(int R, int PF) {
 }
 
 // What an operator sees for one output point (the StreamPoint interface).
-template <int R, int NQ, int NP, int NY, int LH, int LW, int RING, int PR>
+template <int R, int NQ, int NP, int NY, int LH, int LW, int RING, int PR, bool NTS = false>
 struct RingPoint {
     const float (&q)[NQ][NY][RING];
     const float (&lds)[NQ][LH][LW];
@@ -78,7 +78,12 @@ struct RingPoint {
     __device__ __forceinline__ float qy(int f, int k) const { return lds[f][ly + k][lx]; }
     __device__ __forceinline__ float p(int i) const { return pw[i][j][pslot]; }
     // stores v at the point's element of an output field in the same layout
-    __device__ __forceinline__ void store(float *f, float v) const { bstore(rsrc2(f + cbase), vb, soff, v); }
+    __device__ __forceinline__ void store(float *f, float v) const {
+        if constexpr (NTS)
+            bstore_nt(rsrc2(f + cbase), vb, soff, v);
+        else
+            bstore(rsrc2(f + cbase), vb, soff, v);
+    }
 };
 
 template <int R, int NY, int PF, int NQ, int NP, int BY, class Op>
@@ -251,7 +256,7 @@ __device__ __forceinline__ void stream3d_ring_body(const Op &op, const StreamFie
                         const int so = (z - zlo) * plane_bytes;
 #pragma unroll
                         for (int c = 0; c < NY; ++c) {
-                            RingPoint<R, NQ, NP, NY, LH, LW, RING, PR> pt{
+                            RingPoint<R, NQ, NP, NY, LH, LW, RING, PR, streaming_st<Op>::value> pt{
                                 q, lds[buf], pw, c, RY + wy * NY + c, R + lane, x, yb + c, z, cs, cp, DIR, so,
                                 vcol[c], cbase};
                             op.template point<R>(pt, tile_flag, colv[c] + plane_val, true);
